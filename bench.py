@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Z4c zone-cycles per second on one MI355X.
+
+Workload (default): 64 MeshBlocks of 32^3 (128^3 zones, dx = 0.25 on
+[-16,16]^3), FP64, 6th-order finite differences, Brill-Lindquist puncture
+M = 1 at the origin, outflow boundaries, classic RK4 with CFL 0.25.  Inputs
+are synthetic and resident in HBM before timing starts.
+
+Prints one JSON line: the whole-job ZCPS (interior zones x RK4 steps / s),
+the HBM roofline of the dominant kernel (the fused RHS + RK4 stage kernel)
+timed live with HIP events on its own stream, and the CPU oracle timed on
+the host as a baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Z4c zone-cycles/s (RK4, 6th-order FD), FP64 vs batched/FP32; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per zone per stage-kernel launch (classic RK4 on four
+# registers, fused stage): 16 register accesses per field per RK4 step,
+# 22 fields, over 4 launches; FP32 storage with an FP64 accumulator moves
+# 88 bytes per field per step.
+BYTES_PER_ZONE_LAUNCH = {"fp64": 16 * 22 * 8 / 4, "fp32": 88 * 22 / 4}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="bl64x32")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=5)
+    return ap.parse_args()
+
+
+def cpu_baseline(workload):
+    """The oracle (single-threaded C, FP64) on a bounded sample of the same
+    workload: one RK4 step of a 2x2x2-block (64^3-zone) sub-mesh with the same
+    cell size, order and data type; ZCPS scaled per zone."""
+    import oracle
+    import z4c_inputs as zi
+    mesh0, p, _, dt, _ = zi.workload(workload)
+    n = int(mesh0.n[0])
+    h = mesh0.dx0
+    half = n * h
+    mesh = zi.uniform_mesh((2, 2, 2), n, mesh0.g, (-half,) * 3, (half,) * 3, zi.BC_OUTFLOW)
+    data = zi.brill_lindquist(mesh, [(1.0, (0.0, 0.0, 0.0))])
+    om = oracle.OracleMesh(mesh)
+    regs = oracle.Registers(om, data)
+    t0 = time.perf_counter()
+    oracle.rk4_steps(regs, p, dt, 1)
+    sec = time.perf_counter() - t0
+    return {"value": mesh.zones() / sec, "unit": "zone-cycles/s", "cores": 1, "kind": "oracle",
+            "sample": f"one RK4 step of 8 blocks of {n}^3 (dx={h}, order {p['fd_order']}, "
+                      f"Brill-Lindquist) on one host core, {sec:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "halo-exchange design is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2409_10383_amd as z4c
+    import z4c_inputs as zi
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prec = z4c.FP64 if args.precision == "fp64" else z4c.FP32_MIXED
+    mesh, p, data, dt, _ = zi.workload(args.workload)
+    pack = z4c.Pack(mesh, p, prec)
+    pack.upload(z4c.REG_U, data)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        pack.rk4_step(dt, 1)
+    torch.cuda.synchronize()
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    pack.rk4_step(dt, args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    zcps = pack.zones * args.steps / (ms * 1e-3)
+
+    # dominant kernel: per-launch duration from events around each launch
+    pack.profile(True)
+    pack.profile_read(reset=True)
+    pack.rk4_step(dt, args.profile_steps)
+    st_ms, st_n, fill_ms, fill_n = pack.profile_read(reset=True)
+    pack.profile(False)
+    avg_stage_s = st_ms / st_n * 1e-3
+    bpl = BYTES_PER_ZONE_LAUNCH[args.precision] * pack.zones
+    achieved = bpl / avg_stage_s / 1e9
+
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.precision}.json")
+    if os.path.exists(tfile):
+        with open(tfile) as f:
+            t = json.load(f)
+        if t.get("kernel_source_hash") == kernel_hash():
+            traffic = t.get("bytes_per_launch")
+
+    out = {
+        "metric": METRIC,
+        "value": zcps,
+        "unit": "zone-cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64acc",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "blocks": int(mesh.nb),
+                   "block_cells": int(mesh.n[0]), "zones": pack.zones,
+                   "fd_order": p["fd_order"], "ghosts": mesh.g, "dt": dt,
+                   "initial_data": "Brill-Lindquist M=1" if args.workload.startswith("bl") else args.workload},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_stage (fused RHS + RK4 stage)",
+                     "avg_launch_ms": st_ms / st_n, "launches": int(st_n),
+                     "ghost_fill_avg_ms": (fill_ms / fill_n) if fill_n else None},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2409_10383_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

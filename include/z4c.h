@@ -1,0 +1,241 @@
+/*
+ * z4c.h -- C ABI of the MI355X Z4c hot-path library (libz4c.so).
+ *
+ * The library evolves the vacuum Z4c system of "Performance-Portable
+ * Numerical Relativity with AthenaK" (arXiv 2409.10383) on a MeshBlockPack:
+ * a Mesh of cubic MeshBlocks, each an active region plus g ghost layers,
+ * grouped so that one launch covers all of them (Sec. 3).  Ghosts are filled
+ * at every Runge-Kutta stage from neighbour active zones, from boundary
+ * conditions, or at refinement boundaries by Lagrange restriction and
+ * prolongation with n = g+1 points per axis (Sec. 3.1, Eqs. 1-2).  The
+ * right-hand side uses cell-centred finite differences of order 2(g-1) or
+ * lower (Sec. 3 footnote, Sec. 3.2), Kreiss-Oliger dissipation, the 1+log
+ * lapse and Gamma-driver shift, and constraint damping (Sec. 2, Sec. 4.3);
+ * time integration is classic RK4 (Sec. 4.3).
+ *
+ * Conventions shared by every call:
+ *  - Return value: Z4C_OK (0) or a negative Z4C_E* status.  Nothing aborts,
+ *    prints or throws.  z4c_last_error() gives a message for the last failure
+ *    on a pack.
+ *  - Memory: the CALLER owns all device memory.  The library never allocates
+ *    or frees device memory; z4c_pack_query reports the bytes needed for the
+ *    four registers and for a workspace, and z4c_pack_bind takes device
+ *    pointers to them.  Host-side pack metadata is allocated by
+ *    z4c_pack_create and freed by z4c_pack_destroy.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ *    stream).  Calls enqueue work and return; only calls that return host
+ *    values (norms, flags, features) synchronise that stream.
+ *  - Arguments are validated before anything is enqueued; a rejected call
+ *    has no effect (Z4C_EINVAL).
+ *  - A pack is not thread-safe; calls on one pack must be serialised.
+ *
+ * Register layout (device memory, one allocation per register):
+ *  - State registers U, S1, S2: block b starts at element offset
+ *    z4c_block_offset (its state offset); it holds Z4C_NFIELDS fields, field f at
+ *    offset + f*slab_b, each a cube of E_b = n_b + 2g cells, x fastest:
+ *    index ((k*E + j)*E + i), i,j,k in [0,E), active cells at [g, g+n).
+ *    slab_b = E_b^3 rounded up to a multiple of 256 bytes.  Elements are
+ *    double (Z4C_FP64) or float (Z4C_FP32_MIXED).
+ *  - Accumulator A: always double, active cells only: block b at the
+ *    interior offset of z4c_block_offset, field f at + f*n_b^3, x fastest.
+ *  - Interior outputs (z4c_rhs, per-zone constraints) use the layout of A.
+ * Field order (f = 0..21):
+ *   chi, gxx, gxy, gxz, gyy, gyz, gzz, Khat, Axx, Axy, Axz, Ayy, Ayz, Azz,
+ *   Gamx, Gamy, Gamz, Theta, alpha, betax, betay, betaz
+ */
+#ifndef Z4C_H
+#define Z4C_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define Z4C_NFIELDS 22
+#define Z4C_NREG 4
+#define Z4C_NNORM 6
+#define Z4C_NFEAT 16
+
+enum {
+    Z4C_OK = 0,
+    Z4C_EINVAL = -1,       /* invalid argument or pack description          */
+    Z4C_ENOMEM = -2,       /* host allocation failed / workspace too small   */
+    Z4C_EDEVICE = -3,      /* a HIP call failed                              */
+    Z4C_ESTATE = -4,       /* call out of order (e.g. not bound)             */
+    Z4C_ENONFINITE = -5,   /* non-finite value found (finite check enabled)  */
+    Z4C_EUNSUPPORTED = -6  /* valid but not supported by this build          */
+};
+
+enum { Z4C_REG_U = 0, Z4C_REG_S1 = 1, Z4C_REG_S2 = 2, Z4C_REG_A = 3 };
+enum { Z4C_BC_PERIODIC = 0, Z4C_BC_OUTFLOW = 1, Z4C_BC_USER = 2 };
+enum { Z4C_FP64 = 0, Z4C_FP32_MIXED = 1 };
+/* term mask: the full method is Z4C_TERM_ALL; subsets exist for tests */
+enum {
+    Z4C_TERM_PHYS = 1,    /* Z4c terms of chi, g~, Khat, A~, Gamma~, Theta  */
+    Z4C_TERM_GAUGE = 2,   /* 1+log lapse and Gamma-driver shift terms       */
+    Z4C_TERM_ADVECT = 4,  /* beta^k d_k (lapse/shift only with GAUGE)       */
+    Z4C_TERM_DISSIP = 8,  /* Kreiss-Oliger on all 22 fields                 */
+    Z4C_TERM_ALL = 15
+};
+enum {
+    Z4C_FLAG_ENFORCE = 1,       /* det g~ = 1, tr A~ = 0, floors after writes */
+    Z4C_FLAG_CHECK_FINITE = 2   /* z4c_rk4_step checks U for NaN/Inf         */
+};
+
+/* One MeshBlock: cubic, n^3 active cells at refinement `level`, lower
+ * active corner `ilo` in cells of that level (cell size dx0 / 2^level). */
+typedef struct {
+    int32_t level;
+    int32_t n;
+    int32_t ilo[3];
+} z4c_block;
+
+typedef struct {
+    int32_t fd_order;      /* 4, 6 or 8 (centred order 2N)                   */
+    int32_t nghost;        /* g >= N + 1                                     */
+    int32_t precision;     /* Z4C_FP64 or Z4C_FP32_MIXED                     */
+    int32_t bc;            /* Z4C_BC_*                                       */
+    int32_t nroot[3];      /* root-level cells per axis over the domain      */
+    int32_t pad0;
+    double lo[3];          /* domain lower corner                            */
+    double dx0;            /* root-level cell size                           */
+    double ko_sigma;       /* Kreiss-Oliger strength (paper: 0.5)            */
+    double kappa1;         /* constraint damping (paper: 0.02)               */
+    double kappa2;         /* (paper: 0)                                     */
+    double eta;            /* Gamma-driver damping (2/M)                     */
+    double mu_S;           /* Gamma-driver coefficient (1)                   */
+    double chi_floor;      /* floor of chi, also used wherever chi divides   */
+    double alpha_floor;    /* floor of the lapse                             */
+    uint32_t terms;        /* Z4C_TERM_* mask                                */
+    uint32_t flags;        /* Z4C_FLAG_* mask                                */
+} z4c_params;
+
+typedef struct {
+    size_t reg_bytes[Z4C_NREG]; /* bytes of U, S1, S2, A                      */
+    size_t workspace_bytes;     /* bytes of the workspace                     */
+    int64_t nblocks;
+    int64_t zones;              /* active cells of the pack                   */
+    int32_t state_elem_bytes;   /* 8 (FP64) or 4 (FP32_MIXED)                 */
+    int32_t nwork;              /* work items of the fused stage kernel       */
+} z4c_layout;
+
+/* Norm region for z4c_constraints: zones with centre within r_exc of any
+ * listed centre are left out of the norms (ncentres may be 0). */
+typedef struct {
+    int32_t ncentres;
+    int32_t pad;
+    double centres[8][3];
+    double r_exc;
+} z4c_norm_region;
+
+/* Refinement criteria (Sec. 3.3). */
+enum { Z4C_CRIT_CHI_MIN = 0, Z4C_CRIT_DCHI_MAX = 1, Z4C_CRIT_RADIUS = 2 };
+typedef struct {
+    int32_t criterion;     /* Z4C_CRIT_*                                     */
+    int32_t level_max;     /* no +1 at or above this level                   */
+    double chi_thr;        /* chi-min: refine if min chi < chi_thr (0.3)     */
+    double dchi_thr;       /* dchi-max: refine if max |grad chi| > dchi_thr  */
+    double radius;         /* radius: zones within `radius` of `centre` ...  */
+    double centre[3];
+    int32_t radius_level;  /* ... require level >= radius_level              */
+    int32_t pad;
+} z4c_refine_params;
+
+/* ------------------------------------------------------------------ pack */
+
+/* Validate a pack description and build its host metadata (Sec. 3: Mesh,
+ * MeshBlocks, MeshBlockPack).  Checks: fd_order in {4,6,8}; nghost >= N+1
+ * (the Kreiss-Oliger and lopsided stencils reach N+1 cells); every n even
+ * and >= nghost; blocks inside
+ * the domain, not overlapping, covering it; neighbouring levels differ by at
+ * most one (the 2:1 rule, Sec. 3.3) with refinement-boundary stencils that
+ * stay within one level.  Returns Z4C_EINVAL on any violation.  `blocks` is
+ * host memory, copied.  On success *out owns host memory only. */
+int z4c_pack_create(const z4c_params *params, const z4c_block *blocks, int32_t nblocks,
+                    struct z4c_pack **out);
+
+/* Sizes of the registers and the workspace the caller must allocate. */
+int z4c_pack_query(const struct z4c_pack *pack, z4c_layout *out);
+
+/* Element offset of block b in a state register (ghosted layout) and in the
+ * accumulator / interior layout. */
+int z4c_block_offset(const struct z4c_pack *pack, int32_t b, int64_t *state_off,
+                     int64_t *interior_off);
+
+/* Attach caller-owned device memory: regs[Z4C_NREG] (U, S1, S2, A) of at
+ * least reg_bytes[r] each, 256-byte aligned; workspace of at least
+ * workspace_bytes.  Uploads the block, neighbour and interpolation tables
+ * into the workspace on `stream` (the call returns after the upload has been
+ * enqueued; the workspace must not be reused while the pack is bound). */
+int z4c_pack_bind(struct z4c_pack *pack, void *const regs[Z4C_NREG], void *workspace,
+                  size_t workspace_bytes, void *stream);
+
+/* Free host metadata.  Device memory stays the caller's. */
+void z4c_pack_destroy(struct z4c_pack *pack);
+
+/* Message of the last failed call on `pack` ("" if none). */
+const char *z4c_last_error(const struct z4c_pack *pack);
+
+/* ------------------------------------------------------------- hot path */
+
+/* Fill every ghost cell of state register `reg` (U, S1 or S2): copies of
+ * same-level neighbour active zones, periodic wrap or outflow copy of the
+ * nearest active zone at the domain boundary, and Lagrange restriction /
+ * prolongation at refinement boundaries (Sec. 3, Sec. 3.1).  With
+ * Z4C_BC_USER nothing is written. */
+int z4c_fill_ghosts(struct z4c_pack *pack, int32_t reg, void *stream);
+
+/* Z4c right-hand side (Sec. 2; Sec. 4.3 parameters) of state register
+ * src_reg at every active zone, written as double to rhs_out (device, the
+ * interior layout, 22 fields).  Ghosts of src_reg must already be filled. */
+int z4c_rhs(struct z4c_pack *pack, int32_t src_reg, void *rhs_out, void *stream);
+
+/* One classic RK4 stage (stage = 1..4), fused with the RHS and, unless the
+ * boundary condition is USER, preceded by the ghost fill of the stage input:
+ *   1: k1=F(U):  S1 = U + dt/2 k1, A  = U + dt/6 k1
+ *   2: k2=F(S1): S2 = U + dt/2 k2, A += dt/3 k2
+ *   3: k3=F(S2): S1 = U + dt k3,   A += dt/3 k3
+ *   4: k4=F(S1): U  = A + dt/6 k4
+ * followed, with Z4C_FLAG_ENFORCE, by det g~ = 1, trace-free A~ and the
+ * chi/alpha floors on the written state.  A accumulates in double. */
+int z4c_rk4_stage(struct z4c_pack *pack, int32_t stage, double dt, void *stream);
+
+/* nsteps full RK4 steps of U (four stages each). */
+int z4c_rk4_step(struct z4c_pack *pack, double dt, int32_t nsteps, void *stream);
+
+/* Constraint monitors in double: Hamiltonian H, momentum M^i, Theta and
+ * G^i = Gamma~^i - Gamma~_d^i at every active zone of state register `reg`
+ * (ghosts filled first unless USER).  per_zone_out (device, nullable):
+ * interior layout with 8 components (H, Mx, My, Mz, Theta, Gx, Gy, Gz).
+ * norms_out (host, Z4C_NNORM doubles): H_L2, H_Linf, M_L2, M_Linf,
+ * Theta_L2, G_L2, volume-weighted (dV = dx^3) over the zones kept by
+ * `region` (nullable: all).  Synchronises the stream. */
+int z4c_constraints(struct z4c_pack *pack, int32_t reg, void *per_zone_out,
+                    const z4c_norm_region *region, double *norms_out, void *stream);
+
+/* Refinement flags per block (Sec. 3.3): +1 refine, 0 keep, -1 derefine,
+ * from per-block reductions over active zones of state register `reg`.
+ * flags_out: host int8[nblocks].  Synchronises the stream. */
+int z4c_refine_flags(struct z4c_pack *pack, int32_t reg, const z4c_refine_params *rp,
+                     int8_t *flags_out, void *stream);
+
+/* Kernel timing for benchmarks.  With enable = 1, every later stage-kernel
+ * and ghost-fill launch on this pack is bracketed by a pair of HIP events
+ * recorded on the launch stream; z4c_profile_read waits for them and
+ * returns out[0] total stage-kernel milliseconds, out[1] stage launches,
+ * out[2] ghost-fill milliseconds, out[3] fill launches (reset != 0 clears
+ * the totals).  Events are host-side HIP objects; no device memory. */
+int z4c_profile(struct z4c_pack *pack, int32_t enable);
+int z4c_profile_read(struct z4c_pack *pack, double *out, int32_t reset);
+
+/* Finite-difference weights the kernels use (for inspection): centred first
+ * derivative (N+1 values, k = 0..N), centred second derivative (N+1 values),
+ * lopsided (+) first derivative on -(N-1)..N+1 (2N+1 values).  Host only. */
+int z4c_stencil_weights(int32_t fd_order, double *d1, double *d2, double *lop);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,574 @@
+// Host runtime of libz4c: pack validation and geometry (Mesh / MeshBlock /
+// MeshBlockPack, Sec. 3), register and workspace layout, table upload and
+// kernel dispatch behind the C ABI of include/z4c.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#include "../../include/z4c.h"
+#include "kernels.hpp"
+#include "stencils.hpp"
+
+using namespace z4c;
+
+struct z4c_pack {
+    z4c_params p;
+    std::vector<z4c_block> blk;
+    std::vector<BlockDev> bdev;
+    std::vector<WorkItem> work;
+    std::vector<int32_t> map;
+    LookupDev L;
+    bool multilevel = false;
+    int maxghost = 0;
+    int64_t zones = 0;
+    size_t reg_bytes[Z4C_NREG] = {0, 0, 0, 0};
+    // workspace carve-up (byte offsets)
+    size_t ws_blocks = 0, ws_work = 0, ws_map = 0, ws_part = 0, ws_total = 0;
+    // bound memory
+    bool bound = false;
+    void* reg[Z4C_NREG] = {nullptr, nullptr, nullptr, nullptr};
+    char* ws = nullptr;
+    std::vector<double> part_host;
+    std::string err;
+    // optional kernel timing
+    bool prof = false;
+    struct EvPair { hipEvent_t a, b; int kind; };
+    std::vector<EvPair> ev;
+    double prof_acc[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+int fail(z4c_pack* pk, int code, const char* fmt, ...)
+{
+    if (pk) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        pk->err = buf;
+    }
+    return code;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int gcd_i(int a, int b)
+{
+    a = a < 0 ? -a : a;
+    b = b < 0 ? -b : b;
+    while (b) { int t = a % b; a = b; b = t; }
+    return a;
+}
+
+ParamsDev dev_params(const z4c_params& p)
+{
+    ParamsDev d;
+    d.ko_sigma = p.ko_sigma;
+    d.kappa1 = p.kappa1;
+    d.kappa2 = p.kappa2;
+    d.eta = p.eta;
+    d.mu_S = p.mu_S;
+    d.chi_floor = p.chi_floor;
+    d.alpha_floor = p.alpha_floor;
+    d.terms = p.terms;
+    d.enforce = (p.flags & Z4C_FLAG_ENFORCE) ? 1 : 0;
+    return d;
+}
+
+// tile shape of the fused stage kernel for an n^3 block (256 threads)
+void tile_shape(int n, int& ti, int& tj, int& tk)
+{
+    ti = std::min(n, 32);
+    tj = std::min(n, std::max(1, 256 / ti));
+    tk = std::min(n, std::max(1, 256 / (ti * tj)));
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// bracket a launch with events when profiling is on (kind 0 stage, 1 fill)
+struct ProfScope {
+    z4c_pack* pk;
+    hipStream_t s;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(z4c_pack* p, hipStream_t st, int k) : pk(p), s(st), kind(k)
+    {
+        if (!pk->prof) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+        hipEventRecord(a, s);
+    }
+    ~ProfScope()
+    {
+        if (!a) return;
+        hipEventRecord(b, s);
+        pk->ev.push_back({a, b, kind});
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t nblocks,
+                    z4c_pack** out)
+{
+    if (!out) return Z4C_EINVAL;
+    *out = nullptr;
+    if (!params || !blocks || nblocks < 1) return Z4C_EINVAL;
+    const z4c_params& p = *params;
+    if (p.fd_order != 4 && p.fd_order != 6 && p.fd_order != 8) return Z4C_EINVAL;
+    const int N = p.fd_order / 2;
+    if (p.nghost < N + 1 || p.nghost > 8) return Z4C_EINVAL;
+    if (p.precision != Z4C_FP64 && p.precision != Z4C_FP32_MIXED) return Z4C_EINVAL;
+    if (p.bc < Z4C_BC_PERIODIC || p.bc > Z4C_BC_USER) return Z4C_EINVAL;
+    if (!(p.dx0 > 0.0) || !std::isfinite(p.dx0)) return Z4C_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (p.nroot[a] < 1 || !std::isfinite(p.lo[a])) return Z4C_EINVAL;
+    if ((p.terms & ~15u) != 0) return Z4C_EINVAL;
+    if (!(p.chi_floor >= 0.0) || !(p.alpha_floor >= 0.0) || !(p.ko_sigma >= 0.0)) return Z4C_EINVAL;
+
+    z4c_pack* pk = new (std::nothrow) z4c_pack();
+    if (!pk) return Z4C_ENOMEM;
+    pk->p = p;
+    pk->blk.assign(blocks, blocks + nblocks);
+    const int g = p.nghost;
+    int lmax = 0, unit = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        const z4c_block& B = blocks[b];
+        if (B.level < 0 || B.level > 7 || B.n < 2 || (B.n % 2) || B.n < g || B.n > 512) {
+            delete pk;
+            return Z4C_EINVAL;
+        }
+        for (int a = 0; a < 3; ++a) {
+            const int64_t Nl = (int64_t)p.nroot[a] << B.level;
+            if (B.ilo[a] < 0 || (int64_t)B.ilo[a] + B.n > Nl) { delete pk; return Z4C_EINVAL; }
+            unit = gcd_i(unit, B.ilo[a]);
+        }
+        unit = gcd_i(unit, B.n);
+        lmax = std::max(lmax, B.level);
+    }
+    for (int a = 0; a < 3; ++a) unit = gcd_i(unit, p.nroot[a]);
+    // pairwise checks in units of the finest level: no overlap, 2:1 rule
+    {
+        const int F = lmax;
+        double vol = 0.0;
+        for (int b = 0; b < nblocks; ++b) {
+            const double s = std::ldexp(1.0, F - blocks[b].level);
+            vol += std::pow(blocks[b].n * s, 3);
+        }
+        double dom = 1.0;
+        for (int a = 0; a < 3; ++a) dom *= std::ldexp((double)p.nroot[a], F);
+        if (std::fabs(vol - dom) > 0.5) { delete pk; return Z4C_EINVAL; }
+        for (int b = 0; b < nblocks; ++b) {
+            const int64_t sb = int64_t(1) << (F - blocks[b].level);
+            for (int c = b + 1; c < nblocks; ++c) {
+                const int64_t sc = int64_t(1) << (F - blocks[c].level);
+                bool overlap = true, touch = true;
+                for (int a = 0; a < 3; ++a) {
+                    const int64_t b0 = blocks[b].ilo[a] * sb, b1 = (blocks[b].ilo[a] + blocks[b].n) * sb;
+                    const int64_t c0 = blocks[c].ilo[a] * sc, c1 = (blocks[c].ilo[a] + blocks[c].n) * sc;
+                    // the finer block's ghost reach, in finest units
+                    const int64_t reach = (int64_t)g * std::min(sb, sc) * 2;
+                    if (!(b0 < c1 && c0 < b1)) overlap = false;
+                    if (!(b0 - reach < c1 && c0 - reach < b1)) touch = false;
+                }
+                if (overlap) { delete pk; return Z4C_EINVAL; }
+                if (touch && std::abs(blocks[b].level - blocks[c].level) > 1) {
+                    delete pk;
+                    return Z4C_EINVAL;
+                }
+            }
+        }
+    }
+    pk->multilevel = lmax > 0;
+
+    // register layout
+    const size_t esz = p.precision == Z4C_FP64 ? 8 : 4;
+    int64_t off = 0, ioff = 0;
+    pk->bdev.resize(nblocks);
+    for (int b = 0; b < nblocks; ++b) {
+        const z4c_block& B = blocks[b];
+        BlockDev& d = pk->bdev[b];
+        const int E = B.n + 2 * g;
+        const int64_t cells = (int64_t)E * E * E;
+        const int64_t per256 = 256 / (int64_t)esz;
+        d.off = off;
+        d.ioff = ioff;
+        d.slab = (cells + per256 - 1) / per256 * per256;
+        d.n = B.n;
+        d.E = E;
+        d.level = B.level;
+        d.pad = 0;
+        for (int a = 0; a < 3; ++a) d.ilo[a] = B.ilo[a];
+        d.pad2 = 0;
+        d.h = p.dx0 / (double)(1 << B.level);
+        for (int a = 0; a < 3; ++a) d.x0[a] = p.lo[a] + (B.ilo[a] + 0.5) * d.h;
+        off += (int64_t)NF * d.slab;
+        ioff += (int64_t)NF * B.n * B.n * B.n;
+        pk->zones += (int64_t)B.n * B.n * B.n;
+        pk->maxghost = std::max<int>(pk->maxghost, (int)(cells - (int64_t)B.n * B.n * B.n));
+    }
+    pk->reg_bytes[0] = pk->reg_bytes[1] = pk->reg_bytes[2] = align256((size_t)off * esz);
+    pk->reg_bytes[3] = align256((size_t)ioff * 8);
+
+    // work list: tiles of active cells
+    for (int b = 0; b < nblocks; ++b) {
+        int ti, tj, tk;
+        const int n = blocks[b].n;
+        tile_shape(n, ti, tj, tk);
+        for (int k0 = 0; k0 < n; k0 += tk)
+            for (int j0 = 0; j0 < n; j0 += tj)
+                for (int i0 = 0; i0 < n; i0 += ti) {
+                    WorkItem w;
+                    w.block = b;
+                    w.i0 = (int16_t)i0; w.j0 = (int16_t)j0; w.k0 = (int16_t)k0;
+                    w.ni = (int16_t)std::min(ti, n - i0);
+                    w.nj = (int16_t)std::min(tj, n - j0);
+                    w.nk = (int16_t)std::min(tk, n - k0);
+                    pk->work.push_back(w);
+                }
+    }
+
+    // leaf lookup per level, at `unit` granularity
+    std::memset(&pk->L, 0, sizeof(pk->L));
+    pk->L.unit = unit;
+    pk->L.nlev = lmax + 1;
+    int64_t tot = 0;
+    for (int l = 0; l <= lmax; ++l) {
+        pk->L.base[l] = tot;
+        int64_t t = 1;
+        for (int a = 0; a < 3; ++a) {
+            pk->L.dim[l][a] = (int32_t)(((int64_t)p.nroot[a] << l) / unit);
+            t *= pk->L.dim[l][a];
+        }
+        tot += t;
+    }
+    if (tot > (int64_t)1 << 28) { delete pk; return Z4C_EUNSUPPORTED; }
+    pk->map.assign((size_t)tot, -1);
+    for (int b = 0; b < nblocks; ++b) {
+        const z4c_block& B = blocks[b];
+        const int l = B.level, nu = B.n / unit;
+        for (int z = 0; z < nu; ++z)
+            for (int y = 0; y < nu; ++y)
+                for (int x = 0; x < nu; ++x) {
+                    const int64_t X = B.ilo[0] / unit + x, Y = B.ilo[1] / unit + y, Z = B.ilo[2] / unit + z;
+                    pk->map[pk->L.base[l] + (Z * pk->L.dim[l][1] + Y) * pk->L.dim[l][0] + X] = b;
+                }
+    }
+
+    // workspace
+    size_t o = 0;
+    pk->ws_blocks = o; o = align256(o + sizeof(BlockDev) * nblocks);
+    pk->ws_work = o;   o = align256(o + sizeof(WorkItem) * pk->work.size());
+    pk->ws_map = o;    o = align256(o + sizeof(int32_t) * pk->map.size());
+    pk->ws_part = o;   o = align256(o + sizeof(double) * 8 * pk->work.size());
+    pk->ws_total = o;
+    pk->part_host.resize(8 * pk->work.size());
+    *out = pk;
+    return Z4C_OK;
+}
+
+int z4c_pack_query(const z4c_pack* pk, z4c_layout* out)
+{
+    if (!pk || !out) return Z4C_EINVAL;
+    for (int r = 0; r < Z4C_NREG; ++r) out->reg_bytes[r] = pk->reg_bytes[r];
+    out->workspace_bytes = pk->ws_total;
+    out->nblocks = (int64_t)pk->blk.size();
+    out->zones = pk->zones;
+    out->state_elem_bytes = pk->p.precision == Z4C_FP64 ? 8 : 4;
+    out->nwork = (int32_t)pk->work.size();
+    return Z4C_OK;
+}
+
+int z4c_block_offset(const z4c_pack* pk, int32_t b, int64_t* state_off, int64_t* interior_off)
+{
+    if (!pk || b < 0 || b >= (int32_t)pk->blk.size()) return Z4C_EINVAL;
+    if (state_off) *state_off = pk->bdev[b].off;
+    if (interior_off) *interior_off = pk->bdev[b].ioff;
+    return Z4C_OK;
+}
+
+int z4c_pack_bind(z4c_pack* pk, void* const regs[Z4C_NREG], void* workspace, size_t ws_bytes,
+                  void* stream)
+{
+    if (!pk) return Z4C_EINVAL;
+    if (!regs || !workspace) return fail(pk, Z4C_EINVAL, "null register or workspace pointer");
+    if (ws_bytes < pk->ws_total) return fail(pk, Z4C_ENOMEM, "workspace too small: %zu < %zu", ws_bytes, pk->ws_total);
+    for (int r = 0; r < Z4C_NREG; ++r) {
+        if (!regs[r] || (reinterpret_cast<uintptr_t>(regs[r]) & 255))
+            return fail(pk, Z4C_EINVAL, "register %d null or not 256-byte aligned", r);
+    }
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(pk, Z4C_EINVAL, "workspace not 256-byte aligned");
+    hipStream_t s = as_stream(stream);
+    char* ws = static_cast<char*>(workspace);
+    hipError_t e = hipMemcpyAsync(ws + pk->ws_blocks, pk->bdev.data(), sizeof(BlockDev) * pk->bdev.size(),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + pk->ws_work, pk->work.data(), sizeof(WorkItem) * pk->work.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + pk->ws_map, pk->map.data(), sizeof(int32_t) * pk->map.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "table upload: %s", hipGetErrorString(e));
+    for (int r = 0; r < Z4C_NREG; ++r) pk->reg[r] = regs[r];
+    pk->ws = ws;
+    pk->bound = true;
+    pk->err.clear();
+    return Z4C_OK;
+}
+
+void z4c_pack_destroy(z4c_pack* pk)
+{
+    if (!pk) return;
+    for (auto& e : pk->ev) {
+        hipEventDestroy(e.a);
+        hipEventDestroy(e.b);
+    }
+    delete pk;
+}
+
+int z4c_profile(z4c_pack* pk, int32_t enable)
+{
+    if (!pk) return Z4C_EINVAL;
+    pk->prof = enable != 0;
+    return Z4C_OK;
+}
+
+int z4c_profile_read(z4c_pack* pk, double* out, int32_t reset)
+{
+    if (!pk || !out) return Z4C_EINVAL;
+    for (auto& e : pk->ev) {
+        float ms = 0.f;
+        hipError_t r = hipEventSynchronize(e.b);
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms, e.a, e.b);
+        hipEventDestroy(e.a);
+        hipEventDestroy(e.b);
+        if (r != hipSuccess) { pk->ev.clear(); return fail(pk, Z4C_EDEVICE, "profile: %s", hipGetErrorString(r)); }
+        pk->prof_acc[e.kind == 0 ? 0 : 2] += ms;
+        pk->prof_acc[e.kind == 0 ? 1 : 3] += 1.0;
+    }
+    pk->ev.clear();
+    for (int q = 0; q < 4; ++q) out[q] = pk->prof_acc[q];
+    if (reset)
+        for (int q = 0; q < 4; ++q) pk->prof_acc[q] = 0.0;
+    return Z4C_OK;
+}
+
+const char* z4c_last_error(const z4c_pack* pk) { return pk ? pk->err.c_str() : "null pack"; }
+
+int z4c_fill_ghosts(z4c_pack* pk, int32_t reg, void* stream)
+{
+    if (!pk) return Z4C_EINVAL;
+    if (reg < Z4C_REG_U || reg > Z4C_REG_S2) return fail(pk, Z4C_EINVAL, "bad register %d", reg);
+    if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
+    if (pk->p.bc == Z4C_BC_USER) return Z4C_OK;
+    if (pk->multilevel) return fail(pk, Z4C_EUNSUPPORTED, "cross-level ghost fill not built");
+    FillArgs a;
+    a.reg = pk->reg[reg];
+    a.blocks = reinterpret_cast<const BlockDev*>(pk->ws + pk->ws_blocks);
+    a.map = reinterpret_cast<const int32_t*>(pk->ws + pk->ws_map);
+    a.L = pk->L;
+    a.g = pk->p.nghost;
+    a.bc = pk->p.bc;
+    for (int d = 0; d < 3; ++d) a.nroot[d] = pk->p.nroot[d];
+    a.maxghost = pk->maxghost;
+    ProfScope ps(pk, as_stream(stream), 1);
+    hipError_t e = launch_fill(pk->p.precision, a, (int)pk->blk.size(), as_stream(stream));
+    if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "ghost fill launch: %s", hipGetErrorString(e));
+    return Z4C_OK;
+}
+
+static StageArgs stage_args(z4c_pack* pk)
+{
+    StageArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.blocks = reinterpret_cast<const BlockDev*>(pk->ws + pk->ws_blocks);
+    a.work = reinterpret_cast<const WorkItem*>(pk->ws + pk->ws_work);
+    a.P = dev_params(pk->p);
+    a.g = pk->p.nghost;
+    a.A = static_cast<double*>(pk->reg[Z4C_REG_A]);
+    a.U = pk->reg[Z4C_REG_U];
+    return a;
+}
+
+int z4c_rhs(z4c_pack* pk, int32_t src_reg, void* rhs_out, void* stream)
+{
+    if (!pk) return Z4C_EINVAL;
+    if (src_reg < Z4C_REG_U || src_reg > Z4C_REG_S2) return fail(pk, Z4C_EINVAL, "bad register %d", src_reg);
+    if (!rhs_out) return fail(pk, Z4C_EINVAL, "null rhs_out");
+    if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
+    StageArgs a = stage_args(pk);
+    a.src = pk->reg[src_reg];
+    a.rhs_out = static_cast<double*>(rhs_out);
+    a.stage = 0;
+    hipError_t e = launch_stage(pk->p.fd_order / 2, pk->p.precision, a, (int)pk->work.size(), as_stream(stream));
+    if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "rhs launch: %s", hipGetErrorString(e));
+    return Z4C_OK;
+}
+
+int z4c_rk4_stage(z4c_pack* pk, int32_t stage, double dt, void* stream)
+{
+    if (!pk) return Z4C_EINVAL;
+    if (stage < 1 || stage > 4) return fail(pk, Z4C_EINVAL, "bad stage %d", stage);
+    if (!std::isfinite(dt)) return fail(pk, Z4C_EINVAL, "dt not finite");
+    if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
+    static const int src_of[5] = {0, Z4C_REG_U, Z4C_REG_S1, Z4C_REG_S2, Z4C_REG_S1};
+    static const int dst_of[5] = {0, Z4C_REG_S1, Z4C_REG_S2, Z4C_REG_S1, Z4C_REG_U};
+    int rc = z4c_fill_ghosts(pk, src_of[stage], stream);
+    if (rc) return rc;
+    StageArgs a = stage_args(pk);
+    a.src = pk->reg[src_of[stage]];
+    a.dst = pk->reg[dst_of[stage]];
+    a.dt = dt;
+    a.stage = stage;
+    ProfScope ps(pk, as_stream(stream), 0);
+    hipError_t e = launch_stage(pk->p.fd_order / 2, pk->p.precision, a, (int)pk->work.size(), as_stream(stream));
+    if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "stage launch: %s", hipGetErrorString(e));
+    return Z4C_OK;
+}
+
+int z4c_rk4_step(z4c_pack* pk, double dt, int32_t nsteps, void* stream)
+{
+    if (!pk) return Z4C_EINVAL;
+    if (nsteps < 0) return fail(pk, Z4C_EINVAL, "negative nsteps");
+    for (int s = 0; s < nsteps; ++s)
+        for (int st = 1; st <= 4; ++st) {
+            int rc = z4c_rk4_stage(pk, st, dt, stream);
+            if (rc) return rc;
+        }
+    return Z4C_OK;
+}
+
+static int run_diag(z4c_pack* pk, int32_t reg, int mode, void* per_zone, const double* centres,
+                    int ncentres, double r_exc, void* stream)
+{
+    if (reg < Z4C_REG_U || reg > Z4C_REG_S2) return fail(pk, Z4C_EINVAL, "bad register %d", reg);
+    if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
+    int rc = z4c_fill_ghosts(pk, reg, stream);
+    if (rc) return rc;
+    DiagArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.src = pk->reg[reg];
+    a.per_zone = static_cast<double*>(per_zone);
+    a.partial = reinterpret_cast<double*>(pk->ws + pk->ws_part);
+    a.blocks = reinterpret_cast<const BlockDev*>(pk->ws + pk->ws_blocks);
+    a.work = reinterpret_cast<const WorkItem*>(pk->ws + pk->ws_work);
+    a.P = dev_params(pk->p);
+    for (int d = 0; d < 3; ++d) a.lo[d] = pk->p.lo[d];
+    a.ncentres = ncentres;
+    a.mode = mode;
+    for (int e = 0; e < ncentres; ++e)
+        for (int d = 0; d < 3; ++d) a.centres[e][d] = centres[3 * e + d];
+    a.r_exc = r_exc;
+    a.g = pk->p.nghost;
+    hipStream_t s = as_stream(stream);
+    hipError_t e = launch_diag(pk->p.fd_order / 2, pk->p.precision, a, (int)pk->work.size(), s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pk->part_host.data(), a.partial, sizeof(double) * pk->part_host.size(),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "diagnostics: %s", hipGetErrorString(e));
+    return Z4C_OK;
+}
+
+int z4c_constraints(z4c_pack* pk, int32_t reg, void* per_zone_out, const z4c_norm_region* region,
+                    double* norms_out, void* stream)
+{
+    if (!pk) return Z4C_EINVAL;
+    if (!norms_out) return fail(pk, Z4C_EINVAL, "null norms_out");
+    int nc = 0;
+    double cen[24] = {0};
+    double rexc = 0.0;
+    if (region) {
+        if (region->ncentres < 0 || region->ncentres > 8 || !(region->r_exc >= 0.0))
+            return fail(pk, Z4C_EINVAL, "bad norm region");
+        nc = region->ncentres;
+        for (int e = 0; e < nc; ++e)
+            for (int d = 0; d < 3; ++d) cen[3 * e + d] = region->centres[e][d];
+        rexc = region->r_exc;
+    }
+    int rc = run_diag(pk, reg, 0, per_zone_out, cen, nc, rexc, stream);
+    if (rc) return rc;
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (size_t w = 0; w < pk->work.size(); ++w) {
+        const double* q = &pk->part_host[8 * w];
+        s[0] += q[0]; s[1] = std::max(s[1], q[1]); s[2] += q[2]; s[3] = std::max(s[3], q[3]);
+        s[4] += q[4]; s[5] += q[5]; s[6] += q[6];
+    }
+    const double vol = s[6];
+    norms_out[0] = vol > 0 ? std::sqrt(s[0] / vol) : 0.0;
+    norms_out[1] = s[1];
+    norms_out[2] = vol > 0 ? std::sqrt(s[2] / vol) : 0.0;
+    norms_out[3] = s[3];
+    norms_out[4] = vol > 0 ? std::sqrt(s[4] / vol) : 0.0;
+    norms_out[5] = vol > 0 ? std::sqrt(s[5] / vol) : 0.0;
+    return Z4C_OK;
+}
+
+int z4c_refine_flags(z4c_pack* pk, int32_t reg, const z4c_refine_params* rp, int8_t* flags_out,
+                     void* stream)
+{
+    if (!pk) return Z4C_EINVAL;
+    if (!rp || !flags_out) return fail(pk, Z4C_EINVAL, "null argument");
+    if (rp->criterion < Z4C_CRIT_CHI_MIN || rp->criterion > Z4C_CRIT_RADIUS)
+        return fail(pk, Z4C_EINVAL, "bad criterion %d", rp->criterion);
+    int rc = run_diag(pk, reg, 1, nullptr, rp->centre, 1, 0.0, stream);
+    if (rc) return rc;
+    const size_t nb = pk->blk.size();
+    std::vector<double> cmin(nb, INFINITY), gmax(nb, 0.0), rmin(nb, INFINITY);
+    for (size_t w = 0; w < pk->work.size(); ++w) {
+        const double* q = &pk->part_host[8 * w];
+        const int b = pk->work[w].block;
+        cmin[b] = std::min(cmin[b], q[0]);
+        gmax[b] = std::max(gmax[b], q[1]);
+        rmin[b] = std::min(rmin[b], q[2]);
+    }
+    for (size_t b = 0; b < nb; ++b) {
+        int f = 0;
+        const int lev = pk->blk[b].level;
+        if (rp->criterion == Z4C_CRIT_CHI_MIN) {
+            if (cmin[b] < rp->chi_thr) f = 1;
+            else if (cmin[b] > 1.5 * rp->chi_thr) f = -1;
+        } else if (rp->criterion == Z4C_CRIT_DCHI_MAX) {
+            if (gmax[b] > rp->dchi_thr) f = 1;
+            else if (gmax[b] < 0.5 * rp->dchi_thr) f = -1;
+        } else {
+            f = (rmin[b] < rp->radius && lev < rp->radius_level) ? 1 : 0;
+        }
+        if (f > 0 && lev >= rp->level_max) f = 0;
+        if (f < 0 && lev == 0) f = 0;
+        flags_out[b] = (int8_t)f;
+    }
+    return Z4C_OK;
+}
+
+int z4c_stencil_weights(int32_t fd_order, double* d1, double* d2, double* lop)
+{
+    auto fill = [&](auto tag) {
+        constexpr int N = decltype(tag)::value;
+        for (int k = 0; k <= N; ++k) {
+            if (d1) d1[k] = Stencil<N>::D1[k];
+            if (d2) d2[k] = Stencil<N>::D2[k];
+        }
+        for (int k = 0; k < 2 * N + 1; ++k)
+            if (lop) lop[k] = Stencil<N>::LOP[k];
+    };
+    switch (fd_order) {
+    case 4: fill(std::integral_constant<int, 2>()); return Z4C_OK;
+    case 6: fill(std::integral_constant<int, 3>()); return Z4C_OK;
+    case 8: fill(std::integral_constant<int, 4>()); return Z4C_OK;
+    }
+    return Z4C_EINVAL;
+}
+
+}  // extern "C"

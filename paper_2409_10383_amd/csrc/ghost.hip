@@ -1,0 +1,92 @@
+// Same-level ghost fill: every ghost cell of every block takes the value of
+// the active cell that covers its centre, after the domain boundary
+// condition (periodic wrap, or outflow = clamp to the nearest active cell).
+// Ghost cells covered by another refinement level are left to the
+// cross-level fill.
+#include "kernels.hpp"
+
+namespace z4c {
+
+// ghost cell q of a block (0 <= q < E^3 - n^3) -> (i, j, k) in [0, E)
+__device__ __forceinline__ bool ghost_cell(int64_t q, int n, int g, int E, int& i, int& j, int& k)
+{
+    const int64_t nz = 2LL * g * E * E, ny = 2LL * g * E * n, nx = 2LL * g * n * n;
+    if (q < nz) {
+        k = (int)(q / ((int64_t)E * E));
+        const int64_t r = q % ((int64_t)E * E);
+        j = (int)(r / E);
+        i = (int)(r % E);
+        if (k >= g) k += n;
+        return true;
+    }
+    q -= nz;
+    if (q < ny) {
+        k = g + (int)(q / (2LL * g * E));
+        const int64_t r = q % (2LL * g * E);
+        j = (int)(r / E);
+        i = (int)(r % E);
+        if (j >= g) j += n;
+        return true;
+    }
+    q -= ny;
+    if (q < nx) {
+        k = g + (int)(q / (2LL * g * n));
+        const int64_t r = q % (2LL * g * n);
+        j = g + (int)(r / (2 * g));
+        i = (int)(r % (2 * g));
+        if (i >= g) i += n;
+        return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ int leaf_lookup(const FillArgs& a, int level, const int64_t G[3])
+{
+    if (level >= a.L.nlev) return -1;
+    const int u = a.L.unit;
+    const int64_t q0 = G[0] / u, q1 = G[1] / u, q2 = G[2] / u;
+    return a.map[a.L.base[level] + (q2 * a.L.dim[level][1] + q1) * a.L.dim[level][0] + q0];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_fill_same(const FillArgs a)
+{
+    const int b = blockIdx.y;
+    const BlockDev B = a.blocks[b];
+    const int n = B.n, g = a.g, E = B.E;
+    int i, j, k;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (!ghost_cell(q, n, g, E, i, j, k)) return;
+    int64_t G[3] = {(int64_t)B.ilo[0] + i - g, (int64_t)B.ilo[1] + j - g, (int64_t)B.ilo[2] + k - g};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t N = (int64_t)a.nroot[d] << B.level;
+        if (a.bc == 0) {
+            G[d] = G[d] % N;
+            if (G[d] < 0) G[d] += N;
+        } else {
+            G[d] = G[d] < 0 ? 0 : (G[d] >= N ? N - 1 : G[d]);
+        }
+    }
+    const int s = leaf_lookup(a, B.level, G);
+    if (s < 0) return;  // covered by another level
+    const BlockDev SB = a.blocks[s];
+    const int64_t so = SB.off + ((G[2] - SB.ilo[2] + g) * SB.E + (G[1] - SB.ilo[1] + g)) * SB.E +
+                       (G[0] - SB.ilo[0] + g);
+    const int64_t d = B.off + ((int64_t)k * E + j) * E + i;
+    T* r = (T*)a.reg;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) r[d + f * B.slab] = r[so + f * SB.slab];
+}
+
+hipError_t launch_fill(int prec, const FillArgs& a, int nblocks, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.maxghost + 255) / 256), (unsigned)nblocks);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_fill_same<double>, grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_fill_same<float>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace z4c

@@ -1,0 +1,451 @@
+// Per-zone Z4c right-hand side for the HIP kernels.
+//
+// Equations: the vacuum Z4c system with 1+log lapse and Gamma-driver shift
+// that the paper adopts (Sec. 2), with its Sec. 4.3 parameters:
+//   d_t chi   = (2/3) chi (alpha K - d_k beta^k)
+//   d_t g~_ij = -2 alpha A~_ij + g~_ik d_j beta^k + g~_jk d_i beta^k
+//               - (2/3) g~_ij d_k beta^k
+//   d_t Khat  = -D^i D_i alpha + alpha (A~_ij A~^ij + K^2/3)
+//               + kappa1 (1 - kappa2) alpha Theta
+//   d_t A~_ij = chi [-D_i D_j alpha + alpha R_ij]^TF
+//               + alpha (K A~_ij - 2 A~_ik g~^kl A~_lj)
+//               + A~_ik d_j beta^k + A~_jk d_i beta^k - (2/3) A~_ij d_k beta^k
+//   d_t G~^i  = -G~d^j d_j beta^i + (2/3) G~d^i d_j beta^j + g~^jk d_j d_k beta^i
+//               + (1/3) g~^ij d_j d_k beta^k - 2 A~^ij d_j alpha
+//               + 2 alpha (G~^i_jk A~^jk - (3/2) A~^ij d_j chi / chi
+//                          - (1/3) g~^ij d_j (2 Khat + Theta))
+//               - 2 alpha kappa1 (G~^i - G~d^i)
+//   d_t Theta = (alpha/2)(R - A~_ij A~^ij + (2/3) K^2) - alpha kappa1 (2+kappa2) Theta
+//   d_t alpha = -2 alpha Khat,   d_t beta^i = mu_S G~^i - eta beta^i
+// plus beta^k d_k (lopsided) advection and Kreiss-Oliger dissipation,
+// with K = Khat + 2 Theta, R_ij = R~_ij + R^chi_ij, R = chi g~^ij R_ij, the
+// metric-derived G~d^i = g~^jk G~^i_jk, and chi floored where it divides.
+// The evolved G~^i enters only where differentiated, in the damping term
+// and in the shift equation.
+#pragma once
+#include "stencils.hpp"
+#include "z4c_dev.hpp"
+
+namespace z4c {
+
+// symmetric index: xx xy xz yy yz zz
+__host__ __device__ constexpr int S(int i, int j)
+{
+    return (i == j) ? (i == 0 ? 0 : (i == 1 ? 3 : 5)) : (i + j == 1 ? 1 : (i + j == 2 ? 2 : 4));
+}
+// weight of a symmetric pair in a full double contraction
+__host__ __device__ constexpr double SW(int p) { return (p == 0 || p == 3 || p == 5) ? 1.0 : 2.0; }
+__host__ __device__ constexpr int SA(int p) { return p == 0 ? 0 : p == 1 ? 0 : p == 2 ? 0 : p == 3 ? 1 : p == 4 ? 1 : 2; }
+__host__ __device__ constexpr int SB(int p) { return p == 0 ? 0 : p == 1 ? 1 : p == 2 ? 2 : p == 3 ? 1 : p == 4 ? 2 : 2; }
+
+// Derivative operators on a field pointer `p` at the zone (no 1/h factors).
+template <int N, class C, class T>
+__device__ __forceinline__ C fd1(const T* __restrict__ p, int s)
+{
+    C acc = 0;
+#pragma unroll
+    for (int k = 1; k <= N; ++k) acc += (C)Stencil<N>::D1[k] * ((C)p[k * s] - (C)p[-k * s]);
+    return acc;
+}
+
+template <int N, class C, class T>
+__device__ __forceinline__ C fd2(const T* __restrict__ p, int s)
+{
+    const C f0 = (C)p[0];
+    C acc = 0;
+#pragma unroll
+    for (int k = 1; k <= N; ++k) acc += (C)Stencil<N>::D2[k] * (((C)p[k * s] - f0) + ((C)p[-k * s] - f0));
+    return acc;
+}
+
+template <int N, class C, class T>
+__device__ __forceinline__ C fdmix(const T* __restrict__ p, int sa, int sb)
+{
+    C acc = 0;
+#pragma unroll
+    for (int q = 1; q <= N; ++q) {
+        C in = 0;
+#pragma unroll
+        for (int r = 1; r <= N; ++r) {
+            C d = ((C)p[q * sa + r * sb] - (C)p[q * sa - r * sb]) -
+                  ((C)p[-q * sa + r * sb] - (C)p[-q * sa - r * sb]);
+            in += (C)Stencil<N>::D1[r] * d;
+        }
+        acc += (C)Stencil<N>::D1[q] * in;
+    }
+    return acc;
+}
+
+// advection + dissipation along one axis: v*odd + sum_k ev[k] * (pair sums)
+template <int N, class C, class T>
+__device__ __forceinline__ C fadvdiss(const T* __restrict__ p, int s, C v, const C* ev)
+{
+    const C f0 = (C)p[0];
+    C odd = 0, even = 0;
+#pragma unroll
+    for (int k = 1; k <= N + 1; ++k) {
+        const C fp = (C)p[k * s], fm = (C)p[-k * s];
+        odd += (C)lop_odd<N>(k) * (fp - fm);
+        even += ev[k] * ((fp - f0) + (fm - f0));
+    }
+    return v * odd + even;
+}
+
+// division by chi is done in double whatever C is
+template <class C> __device__ __forceinline__ C inv_chi(C chi, double floor_)
+{
+    double c = (double)chi;
+    if (c < floor_) c = floor_;
+    return (C)(1.0 / c);
+}
+
+// The RHS of one zone.  `z` points at field 0 of the zone in a ghosted
+// state register; fields are `slab` elements apart; sy, sz the row and
+// plane strides.  Returns the 22 centre values in v and the RHS in rhs.
+template <int N, class T, class C, bool CONS = false>
+__device__ __forceinline__ void zone_rhs(const T* __restrict__ z, int64_t slab, int sy, int sz,
+                                         C ih, const ParamsDev& P, C* __restrict__ rhs,
+                                         C* __restrict__ v)
+{
+    // With CONS, rhs[0..7] receives the constraint monitors instead:
+    // H, M^x, M^y, M^z, Theta, G^x, G^y, G^z.
+    const int st[3] = {1, sy, sz};
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v[f] = (C)z[f * slab];
+
+    const C chi = v[F_CHI], Kh = v[F_KH], Th = v[F_TH], al = v[F_ALPHA];
+    C g[6], A[6], Gam[3], be[3];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) { g[p] = v[F_GXX + p]; A[p] = v[F_AXX + p]; }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { Gam[i] = v[F_GAMX + i]; be[i] = v[F_BETAX + i]; }
+
+    // ---- first derivatives (d[a] = d_a)
+    C dg[3][6], dchi[3], dal[3], dKh[3], dTh[3], dbe[3][3], dGam[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int s = st[a];
+#pragma unroll
+        for (int p = 0; p < 6; ++p) dg[a][p] = ih * fd1<N, C>(z + (F_GXX + p) * slab, s);
+        dchi[a] = ih * fd1<N, C>(z + F_CHI * slab, s);
+        dal[a] = ih * fd1<N, C>(z + F_ALPHA * slab, s);
+        dKh[a] = ih * fd1<N, C>(z + F_KH * slab, s);
+        dTh[a] = ih * fd1<N, C>(z + F_TH * slab, s);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            dbe[a][i] = ih * fd1<N, C>(z + (F_BETAX + i) * slab, s);
+            dGam[a][i] = ih * fd1<N, C>(z + (F_GAMX + i) * slab, s);
+        }
+    }
+
+    // ---- inverse conformal metric
+    C gu[6];
+    {
+        const C c0 = g[3] * g[5] - g[4] * g[4];
+        const C c1 = g[2] * g[4] - g[1] * g[5];
+        const C c2 = g[1] * g[4] - g[2] * g[3];
+        const C det = g[0] * c0 + g[1] * c1 + g[2] * c2;
+        const C id = (C)1 / det;
+        gu[0] = c0 * id;
+        gu[1] = c1 * id;
+        gu[2] = c2 * id;
+        gu[3] = (g[0] * g[5] - g[2] * g[2]) * id;
+        gu[4] = (g[1] * g[2] - g[0] * g[4]) * id;
+        gu[5] = (g[0] * g[3] - g[1] * g[1]) * id;
+    }
+    const C ic = inv_chi<C>(chi, P.chi_floor);
+    const C K = Kh + (C)2 * Th;
+
+    // ---- Christoffel symbols: Gl[k][ij] = G~_kij, Gu[k][ij] = G~^k_ij
+    C Gl[3][6], Gu[3][6], Gd[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const int i = SA(p), j = SB(p);
+            Gl[k][p] = (C)0.5 * (dg[i][S(j, k)] + dg[j][S(i, k)] - dg[k][p]);
+        }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int p = 0; p < 6; ++p)
+            Gu[k][p] = gu[S(k, 0)] * Gl[0][p] + gu[S(k, 1)] * Gl[1][p] + gu[S(k, 2)] * Gl[2][p];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        C s = 0;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) s += (C)SW(p) * gu[p] * Gu[i][p];
+        Gd[i] = s;
+    }
+
+    // ---- A~^ij, A~_ij A~^ij, A~_ik g~^kl (mixed)
+    C Am[3][3];  // Am[i][l] = A~_ik g~^kl
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+            Am[i][l] = A[S(i, 0)] * gu[S(0, l)] + A[S(i, 1)] * gu[S(1, l)] + A[S(i, 2)] * gu[S(2, l)];
+    C Au[6];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        const int i = SA(p), j = SB(p);
+        Au[p] = gu[S(i, 0)] * Am[0][j] + gu[S(i, 1)] * Am[1][j] + gu[S(i, 2)] * Am[2][j];
+    }
+    C AA = 0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) AA += (C)SW(p) * A[p] * Au[p];
+
+    // ---- second derivatives, contracted as they are produced
+    // Rt[ij] starts with -1/2 g~^lm d_l d_m g~_ij
+    C Rt[6], ddchi[6], ddal[6], Lb[3], Bj[3];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) Rt[p] = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { Lb[i] = 0; Bj[i] = 0; }
+    const C ih2 = ih * ih;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const int a = SA(q), b = SB(q);
+        const C wq = (C)(-0.5 * SW(q)) * gu[q] * ih2;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const T* pf = z + (F_GXX + p) * slab;
+            const C d = (a == b) ? fd2<N, C>(pf, st[a]) : fdmix<N, C>(pf, st[a], st[b]);
+            Rt[p] += wq * d;
+        }
+        {
+            const T* pf = z + F_CHI * slab;
+            ddchi[q] = ih2 * ((a == b) ? fd2<N, C>(pf, st[a]) : fdmix<N, C>(pf, st[a], st[b]));
+            pf = z + F_ALPHA * slab;
+            ddal[q] = ih2 * ((a == b) ? fd2<N, C>(pf, st[a]) : fdmix<N, C>(pf, st[a], st[b]));
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const T* pf = z + (F_BETAX + i) * slab;
+            const C d = ih2 * ((a == b) ? fd2<N, C>(pf, st[a]) : fdmix<N, C>(pf, st[a], st[b]));
+            Lb[i] += (C)SW(q) * gu[q] * d;          // g~^jk d_j d_k beta^i
+            // B_j = d_j d_k beta^k: pair q=(a,b) contributes to B_a if i==b, B_b if i==a
+            if (i == b) Bj[a] += d;
+            if (a != b && i == a) Bj[b] += d;
+        }
+    }
+
+    // ---- rest of the conformal Ricci tensor
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        const int i = SA(p), j = SB(p);
+        C s = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            s += (C)0.5 * (g[S(k, i)] * dGam[j][k] + g[S(k, j)] * dGam[i][k]) +
+                 Gd[k] * (C)0.5 * (Gl[i][S(j, k)] + Gl[j][S(i, k)]);
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                C t = 0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    t += Gu[k][S(l, i)] * Gl[j][S(k, m)] + Gu[k][S(l, j)] * Gl[i][S(k, m)] +
+                         Gu[k][S(i, m)] * Gl[k][S(l, j)];
+                s += gu[S(l, m)] * t;
+            }
+        Rt[p] += s;
+    }
+
+    // ---- conformal-factor part and the full Ricci tensor
+    C Rij[6];
+    {
+        C Dchi[6], trD = 0, dc2 = 0;
+#pragma unroll
+        for (int p = 0; p < 6; ++p)
+            Dchi[p] = ddchi[p] - (Gu[0][p] * dchi[0] + Gu[1][p] * dchi[1] + Gu[2][p] * dchi[2]);
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            trD += (C)SW(p) * gu[p] * Dchi[p];
+            dc2 += (C)SW(p) * gu[p] * dchi[SA(p)] * dchi[SB(p)];
+        }
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const int i = SA(p), j = SB(p);
+            Rij[p] = Rt[p] + (C)0.5 * ic * Dchi[p] + (C)0.5 * ic * g[p] * trD -
+                     (C)0.25 * ic * ic * dchi[i] * dchi[j] - (C)0.75 * ic * ic * g[p] * dc2;
+        }
+    }
+    C Rs = 0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) Rs += (C)SW(p) * gu[p] * Rij[p];
+    Rs *= chi;
+
+    // ---- D_i D_j alpha
+    C DDa[6], trDDa = 0;
+    {
+        C cda = 0;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const int i = SA(p), j = SB(p);
+            cda += (C)SW(p) * gu[p] * (C)0.5 * (dchi[i] * dal[j] + dchi[j] * dal[i]);
+        }
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const int i = SA(p), j = SB(p);
+            DDa[p] = ddal[p] - (Gu[0][p] * dal[0] + Gu[1][p] * dal[1] + Gu[2][p] * dal[2]) +
+                     (C)0.5 * ic * (dchi[i] * dal[j] + dchi[j] * dal[i] - g[p] * cda);
+            trDDa += (C)SW(p) * gu[p] * DDa[p];
+        }
+        trDDa *= chi;
+    }
+
+    if constexpr (CONS) {
+        // H = R - A~_ij A~^ij + (2/3) K^2
+        rhs[0] = Rs - AA + (C)(2.0 / 3.0) * K * K;
+        // M^i = d_j A~^ij + G~^i_jk A~^jk - (2/3) g~^ij d_j K - (3/2) A~^ij d_j chi / chi
+        C dA[3][6], dgu[3][6];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int p = 0; p < 6; ++p) dA[a][p] = ih * fd1<N, C>(z + (F_AXX + p) * slab, st[a]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                const int i = SA(p), j = SB(p);
+                C s = 0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) s -= gu[S(i, c)] * gu[S(j, d)] * dg[a][S(c, d)];
+                dgu[a][p] = s;
+            }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            C s = 0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int l = 0; l < 3; ++l)
+                        s += dgu[j][S(i, k)] * gu[S(j, l)] * A[S(k, l)] +
+                             gu[S(i, k)] * dgu[j][S(j, l)] * A[S(k, l)] +
+                             gu[S(i, k)] * gu[S(j, l)] * dA[j][S(k, l)];
+#pragma unroll
+            for (int p = 0; p < 6; ++p) s += (C)SW(p) * Gu[i][p] * Au[p];
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                s -= (C)(2.0 / 3.0) * gu[S(i, j)] * (dKh[j] + (C)2 * dTh[j]) +
+                     (C)1.5 * Au[S(i, j)] * dchi[j] * ic;
+            rhs[1 + i] = s;
+            rhs[5 + i] = Gam[i] - Gd[i];
+        }
+        rhs[4] = Th;
+        return;
+    }
+
+    const C divb = dbe[0][0] + dbe[1][1] + dbe[2][2];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) rhs[f] = 0;
+
+    if (P.terms & 1u) {
+        rhs[F_CHI] = (C)(2.0 / 3.0) * chi * (al * K - divb);
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const int i = SA(p), j = SB(p);
+            C s = (C)-2 * al * A[p] - (C)(2.0 / 3.0) * g[p] * divb;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s += g[S(i, k)] * dbe[j][k] + g[S(j, k)] * dbe[i][k];
+            rhs[F_GXX + p] = s;
+        }
+        rhs[F_KH] = -trDDa + al * (AA + K * K / (C)3) + (C)(P.kappa1 * (1.0 - P.kappa2)) * al * Th;
+        C X[6], trX = 0;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            X[p] = -DDa[p] + al * Rij[p];
+            trX += (C)SW(p) * gu[p] * X[p];
+        }
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const int i = SA(p), j = SB(p);
+            C s = chi * (X[p] - g[p] * trX / (C)3);
+            const C AgA = Am[i][0] * A[S(0, j)] + Am[i][1] * A[S(1, j)] + Am[i][2] * A[S(2, j)];
+            s += al * (K * A[p] - (C)2 * AgA);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s += A[S(i, k)] * dbe[j][k] + A[S(j, k)] * dbe[i][k];
+            s -= (C)(2.0 / 3.0) * A[p] * divb;
+            rhs[F_AXX + p] = s;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            C s = (C)(2.0 / 3.0) * Gd[i] * divb - (Gd[0] * dbe[0][i] + Gd[1] * dbe[1][i] + Gd[2] * dbe[2][i]);
+            s += Lb[i] + (gu[S(i, 0)] * Bj[0] + gu[S(i, 1)] * Bj[1] + gu[S(i, 2)] * Bj[2]) / (C)3;
+            s -= (C)2 * (Au[S(i, 0)] * dal[0] + Au[S(i, 1)] * dal[1] + Au[S(i, 2)] * dal[2]);
+            C t = 0;
+#pragma unroll
+            for (int p = 0; p < 6; ++p) t += (C)SW(p) * Gu[i][p] * Au[p];
+            t -= (C)1.5 * ic * (Au[S(i, 0)] * dchi[0] + Au[S(i, 1)] * dchi[1] + Au[S(i, 2)] * dchi[2]);
+            t -= (gu[S(i, 0)] * ((C)2 * dKh[0] + dTh[0]) + gu[S(i, 1)] * ((C)2 * dKh[1] + dTh[1]) +
+                  gu[S(i, 2)] * ((C)2 * dKh[2] + dTh[2])) / (C)3;
+            s += (C)2 * al * t;
+            s -= (C)2 * al * (C)P.kappa1 * (Gam[i] - Gd[i]);
+            rhs[F_GAMX + i] = s;
+        }
+        rhs[F_TH] = (C)0.5 * al * (Rs - AA + (C)(2.0 / 3.0) * K * K) -
+                    al * (C)(P.kappa1 * (2.0 + P.kappa2)) * Th;
+    }
+    if (P.terms & 2u) {
+        rhs[F_ALPHA] = (C)-2 * al * Kh;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) rhs[F_BETAX + i] = (C)P.mu_S * Gam[i] - (C)P.eta * be[i];
+    }
+
+    // ---- advection (lopsided, upwinded by the sign of beta) + Kreiss-Oliger
+    const bool adv = (P.terms & 4u) != 0;
+    const bool adv_gauge = adv && (P.terms & 2u);
+    const C sig = (P.terms & 8u) ? (C)P.ko_sigma : (C)0;
+    C ev[3][N + 2], evk[N + 2];  // even coefficients with / without advection
+#pragma unroll
+    for (int k = 1; k <= N + 1; ++k) {
+        evk[k] = sig * (C)Stencil<N>::KO[k];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            ev[a][k] = (adv ? (C)fabs((double)be[a]) * (C)lop_even<N>(k) : (C)0) + evk[k];
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const bool gauge_field = (f == F_ALPHA || f >= F_BETAX);
+        const bool a_on = gauge_field ? adv_gauge : adv;
+        C s = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const C va = a_on ? be[a] : (C)0;
+            s += fadvdiss<N, C>(z + f * slab, st[a], va, a_on ? ev[a] : evk);
+        }
+        rhs[f] += ih * s;
+    }
+}
+
+// Algebraic constraints and floors on one zone's state, in double.
+__device__ __forceinline__ void enforce_zone(double* u, const ParamsDev& P)
+{
+    double g0 = u[F_GXX], g1 = u[F_GXY], g2 = u[F_GXZ], g3 = u[F_GYY], g4 = u[F_GYZ], g5 = u[F_GZZ];
+    const double det = g0 * (g3 * g5 - g4 * g4) - g1 * (g1 * g5 - g4 * g2) + g2 * (g1 * g4 - g3 * g2);
+    const double s = 1.0 / cbrt(det);
+    g0 *= s; g1 *= s; g2 *= s; g3 *= s; g4 *= s; g5 *= s;
+    const double c0 = g3 * g5 - g4 * g4, c1 = g2 * g4 - g1 * g5, c2 = g1 * g4 - g2 * g3;
+    const double d = g0 * c0 + g1 * c1 + g2 * c2;
+    const double gu0 = c0 / d, gu1 = c1 / d, gu2 = c2 / d, gu3 = (g0 * g5 - g2 * g2) / d,
+                 gu4 = (g1 * g2 - g0 * g4) / d, gu5 = (g0 * g3 - g1 * g1) / d;
+    const double tr = gu0 * u[F_AXX] + gu3 * u[F_AYY] + gu5 * u[F_AZZ] +
+                      2.0 * (gu1 * u[F_AXY] + gu2 * u[F_AXZ] + gu4 * u[F_AYZ]);
+    u[F_GXX] = g0; u[F_GXY] = g1; u[F_GXZ] = g2; u[F_GYY] = g3; u[F_GYZ] = g4; u[F_GZZ] = g5;
+    u[F_AXX] -= g0 * tr / 3.0;
+    u[F_AXY] -= g1 * tr / 3.0;
+    u[F_AXZ] -= g2 * tr / 3.0;
+    u[F_AYY] -= g3 * tr / 3.0;
+    u[F_AYZ] -= g4 * tr / 3.0;
+    u[F_AZZ] -= g5 * tr / 3.0;
+    if (u[F_CHI] < P.chi_floor) u[F_CHI] = P.chi_floor;
+    if (u[F_ALPHA] < P.alpha_floor) u[F_ALPHA] = P.alpha_floor;
+}
+
+}  // namespace z4c

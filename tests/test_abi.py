@@ -1,0 +1,96 @@
+"""C-ABI contract checks that need no GPU: the library loads and exports
+every call include/z4c.h declares, its stencil constants equal the exact
+rational weights, and invalid pack descriptions are rejected at create."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2409_10383_amd as z
+import z4c_inputs as zi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"\b(z4c_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_call():
+    L = z.lib()
+    decl = declared_functions()
+    assert len(decl) >= 13
+    for name in decl:
+        assert hasattr(L, name), name
+    assert set(z.EXPORTS) <= set(decl)
+
+
+@pytest.mark.parametrize("order", [4, 6, 8])
+def test_kernel_stencils_equal_exact_weights(order):
+    N = order // 2
+    d1, d2, lop = z.stencil_weights(order)
+    c1 = oracle.fd_weights(1, list(range(-N, N + 1)))
+    c2 = oracle.fd_weights(2, list(range(-N, N + 1)))
+    cl = oracle.fd_weights(1, list(range(-(N - 1), N + 2)))
+    np.testing.assert_allclose(d1[1:], c1[N + 1:], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(d2, c2[N:], rtol=0, atol=4e-15)
+    np.testing.assert_allclose(lop, cl, rtol=0, atol=4e-15)
+
+
+def _create(mesh, p, precision=0):
+    h = C.c_void_p()
+    rc = z.lib().z4c_pack_create(C.byref(z.make_params(mesh, p, precision)), z.make_blocks(mesh),
+                                 mesh.nb, C.byref(h))
+    if rc == 0:
+        z.lib().z4c_pack_destroy(h)
+    return rc
+
+
+def test_valid_pack_accepted_and_layout():
+    mesh, p, _, _, _ = zi.workload("bl64x32")
+    h = C.c_void_p()
+    assert z.lib().z4c_pack_create(C.byref(z.make_params(mesh, p)), z.make_blocks(mesh), mesh.nb,
+                                   C.byref(h)) == 0
+    lay = z.Layout()
+    assert z.lib().z4c_pack_query(h, C.byref(lay)) == 0
+    E = 32 + 8
+    slab = (E ** 3 * 8 + 255) // 256 * 256
+    assert lay.reg_bytes[0] == 64 * 22 * slab
+    assert lay.reg_bytes[3] == 64 * 22 * 32 ** 3 * 8
+    assert lay.zones == 64 * 32 ** 3 and lay.nblocks == 64
+    so, io = C.c_int64(), C.c_int64()
+    assert z.lib().z4c_block_offset(h, 5, C.byref(so), C.byref(io)) == 0
+    assert so.value == 5 * 22 * slab // 8 and io.value == 5 * 22 * 32 ** 3
+    assert z.lib().z4c_block_offset(h, 64, C.byref(so), C.byref(io)) == -1
+    z.lib().z4c_pack_destroy(h)
+
+
+def test_invalid_descriptions_rejected():
+    mesh, p, _, _, _ = zi.workload("periodic16")
+    assert _create(mesh, p) == 0
+    bad = dict(p, fd_order=5)
+    assert _create(mesh, bad) == -1
+    m2 = zi.uniform_mesh((1, 1, 1), 16, 2, (0,) * 3, (1,) * 3, zi.BC_PERIODIC)
+    assert _create(m2, dict(p, fd_order=6)) == -1          # g < N + 1
+    m3 = zi.uniform_mesh((2, 1, 1), 8, 4, (0, 0, 0), (2, 1, 1), zi.BC_OUTFLOW)
+    m3.ilo[1] = m3.ilo[0]                                     # overlap / hole
+    assert _create(m3, p) == -1
+    m4 = zi.uniform_mesh((1, 1, 1), 16, 4, (0,) * 3, (1,) * 3, zi.BC_PERIODIC)
+    m4.n[0] = 15                                              # odd size
+    assert _create(m4, p) == -1
+    # 2:1 violation: a level-2 block touching a level-0 block
+    base = zi.uniform_mesh((2, 2, 2), 8, 4, (0,) * 3, (16,) * 3, zi.BC_OUTFLOW)
+    fine = zi.refine_blocks(base, [0])
+    finer = zi.refine_blocks(fine, [7])   # corner child of the refined block
+    assert _create(finer, p) == -1
+    assert _create(fine, p) == 0
+    assert _create(mesh, p, precision=3) == -1
+    assert _create(mesh, dict(p, terms=99)) == -1

@@ -1,0 +1,163 @@
+"""GPU parity: every C-ABI call of libz4c against the oracle on the same
+seeded inputs (relative L-infinity per field <= 1e-12 in FP64; integer
+outputs exact)."""
+import numpy as np
+import pytest
+
+import oracle
+import z4c_inputs as zi
+from _parity import assert_parity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def z():
+    import paper_2409_10383_amd as m
+    return m
+
+
+def small_bl(order, nblk=2, n=8, bc=zi.BC_OUTFLOW, perturb=True):
+    g = order // 2 + 1
+    mesh = zi.uniform_mesh((nblk,) * 3, n, g, (-4.0,) * 3, (4.0,) * 3, bc)
+    data = zi.brill_lindquist(mesh, [(1.0, (0.0, 0.0, 0.0))])
+    if perturb:
+        data = zi.add_perturbation(mesh, data, seed=9, amp=1e-4)
+        for b in data:
+            b[19:22] += 0.05   # shift of both signs after perturbation
+            b[19] -= 0.08
+    return mesh, zi.params_default(order), data
+
+
+def gpu_rhs(mesh, p, data, precision=0):
+    pk = z().Pack(mesh, p, precision)
+    pk.upload(z().REG_U, data)
+    pk.fill_ghosts(z().REG_U)
+    r = pk.rhs(z().REG_U)
+    torch.cuda.synchronize()
+    return pk, pk.split_interior(r)
+
+
+def ora_rhs(mesh, p, data):
+    om = oracle.OracleMesh(mesh)
+    return oracle.rhs(om, p, om.scatter(data))
+
+
+def test_flat_space_rhs_is_exactly_zero():
+    mesh = zi.uniform_mesh((2, 1, 1), 16, 4, (0, 0, 0), (2, 1, 1), zi.BC_OUTFLOW)
+    _, r = gpu_rhs(mesh, zi.params_default(6), zi.flat(mesh))
+    for b in r:
+        assert np.all(b == 0.0)
+
+
+def test_ghost_fill_bitwise_equal():
+    for bc in (zi.BC_PERIODIC, zi.BC_OUTFLOW):
+        mesh = zi.uniform_mesh((2, 3, 2), 8, 4, (0, 0, 0), (2, 3, 2), bc)
+        rng = np.random.default_rng(1)
+        data = [rng.standard_normal((22, 8, 8, 8)) for _ in range(mesh.nb)]
+        pk = z().Pack(mesh, zi.params_default(6))
+        pk.upload(z().REG_U, data)
+        pk.fill_ghosts(z().REG_U)
+        got = pk.download(z().REG_U, ghosted=True)
+        om = oracle.OracleMesh(mesh)
+        u = om.scatter(data)
+        oracle.fill_ghosts(om, u)
+        for b in range(mesh.nb):
+            np.testing.assert_array_equal(got[b], om.block_view(u, b))
+
+
+def test_rhs_parity_periodic16():
+    """The 16^3 periodic block, 4th order, seeded sinusoids (one RK4 step)."""
+    mesh, p, data, dt, _ = zi.workload("periodic16")
+    _, rg = gpu_rhs(mesh, p, data)
+    assert_parity(rg, ora_rhs(mesh, p, data), what="rhs periodic16")
+
+
+@pytest.mark.parametrize("order", [4, 6, 8])
+def test_rhs_parity_multiblock_outflow(order):
+    mesh, p, data = small_bl(order)
+    _, rg = gpu_rhs(mesh, p, data)
+    assert_parity(rg, ora_rhs(mesh, p, data), what=f"rhs order {order}")
+
+
+@pytest.mark.parametrize("terms", [1, 2, 4, 8, 5, 15])
+def test_rhs_parity_term_masks(terms):
+    mesh, p, data = small_bl(6)
+    p["terms"] = terms
+    _, rg = gpu_rhs(mesh, p, data)
+    assert_parity(rg, ora_rhs(mesh, p, data), what=f"terms {terms}")
+
+
+def test_rk4_stages_parity_periodic16():
+    mesh, p, data, dt, _ = zi.workload("periodic16")
+    pk = z().Pack(mesh, p)
+    pk.upload(z().REG_U, data)
+    om = oracle.OracleMesh(mesh)
+    regs = oracle.Registers(om, data)
+    for stage in (1, 2, 3, 4):
+        pk.rk4_stage(stage, dt)
+        oracle.rk4_stage(regs, p, stage, dt)
+        torch.cuda.synchronize()
+        reg = {1: 1, 2: 2, 3: 1, 4: 0}[stage]
+        ora = {0: regs.U, 1: regs.S1, 2: regs.S2}[reg]
+        assert_parity(pk.download(reg), om.interiors(ora), what=f"stage {stage}", mode="state")
+        if stage < 4:
+            acc = pk.split_interior(pk.acc_view())
+            assert_parity(acc, om.interiors(regs.A), what=f"accumulator stage {stage}", mode="state")
+
+
+def test_rk4_steps_parity_bl():
+    """Two full RK4 steps of a Brill-Lindquist pack, 6th order, outflow."""
+    mesh = zi.uniform_mesh((2, 2, 2), 16, 4, (-8.0,) * 3, (8.0,) * 3, zi.BC_OUTFLOW)
+    data = zi.brill_lindquist(mesh, [(1.0, (0.0, 0.0, 0.0))])
+    p = zi.params_default(6)
+    dt = 0.25 * mesh.dx0
+    pk = z().Pack(mesh, p)
+    pk.upload(z().REG_U, data)
+    pk.rk4_step(dt, 2)
+    om = oracle.OracleMesh(mesh)
+    regs = oracle.Registers(om, data)
+    oracle.rk4_steps(regs, p, dt, 2)
+    torch.cuda.synchronize()
+    assert_parity(pk.download(0), om.interiors(regs.U), what="2 steps BL", mode="state")
+
+
+def test_constraints_parity():
+    mesh, p, data = small_bl(6)
+    pk = z().Pack(mesh, p)
+    pk.upload(z().REG_U, data)
+    cz, norms = pk.constraints(z().REG_U, exclude=[(0.0, 0.0, 0.0)], r_exc=1.0)
+    om = oracle.OracleMesh(mesh)
+    co, no = oracle.constraints(om, p, om.scatter(data), exclude=[(0.0, 0.0, 0.0)], r_exc=1.0)
+    assert_parity(pk.split_interior(cz, 8), co, what="constraints")
+    np.testing.assert_allclose(norms, no, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("crit", [0, 1, 2])
+def test_refine_flags_exact(crit):
+    mesh = zi.uniform_mesh((4, 4, 4), 8, 4, (-8,) * 3, (8,) * 3, zi.BC_OUTFLOW)
+    data = zi.brill_lindquist(mesh, [(1.0, (0.5, 0.0, 0.0))])
+    p = zi.params_default(6)
+    pk = z().Pack(mesh, p)
+    pk.upload(z().REG_U, data)
+    kw = dict(chi_thr=0.3, dchi_thr=0.05, level_max=5, radius=3.0, centre=(0.0, 0.0, 0.0),
+              radius_level=1)
+    fg = pk.refine_flags(z().REG_U, crit, **kw)
+    om = oracle.OracleMesh(mesh)
+    fo = oracle.refine_flags(om, p, om.scatter(data), crit, **kw)
+    np.testing.assert_array_equal(fg, fo)
+    assert (fg != 0).any()
+
+
+def test_bl64x32_full_size_rhs_parity():
+    """The 64 x 32^3 Brill-Lindquist pack at full size (the benchmarked
+    configuration): RHS of the initial data against the oracle."""
+    mesh, p, data, dt, _ = zi.workload("bl64x32")
+    _, rg = gpu_rhs(mesh, p, data)
+    assert_parity(rg, ora_rhs(mesh, p, data), what="rhs bl64x32")
