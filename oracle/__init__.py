@@ -44,6 +44,8 @@ def lib():
         L.or_fd_weights.argtypes = [C.c_int, C.c_int, dp, dp]
         L.or_fill_ghosts.argtypes = [C.POINTER(_Mesh), dp]
         L.or_rhs.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), dp, dp]
+        L.or_rhs_blocks.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), dp, dp,
+                                    C.POINTER(C.c_int8)]
         L.or_rk4_stage.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), C.c_int, C.c_double,
                                    dp, dp, dp, dp]
         L.or_constraints.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), dp, dp, C.c_int, dp,
@@ -153,12 +155,18 @@ def fill_ghosts(om: OracleMesh, u: np.ndarray) -> None:
         raise RuntimeError(f"oracle ghost fill failed ({rc})")
 
 
-def rhs(om: OracleMesh, params: dict, u: np.ndarray, fill: bool = True):
-    """Per-block RHS interiors (22, n, n, n); fills ghosts of u first."""
+def rhs(om: OracleMesh, params: dict, u: np.ndarray, fill: bool = True, blocks=None):
+    """Per-block RHS interiors (22, n, n, n); fills ghosts of u first.  With
+    `blocks`, only those blocks are computed (the others stay zero)."""
     if fill:
         fill_ghosts(om, u)
     r = np.zeros(int(om.ioff[-1]))
-    rc = lib().or_rhs(C.byref(om.c), C.byref(make_params(params)), _dp(u), _dp(r))
+    only = None
+    if blocks is not None:
+        mask = np.zeros(om.mesh.nb, np.int8)
+        mask[list(blocks)] = 1
+        only = mask.ctypes.data_as(C.POINTER(C.c_int8))
+    rc = lib().or_rhs_blocks(C.byref(om.c), C.byref(make_params(params)), _dp(u), _dp(r), only)
     if rc:
         raise RuntimeError(f"oracle rhs failed ({rc})")
     return om.split_interior(r)

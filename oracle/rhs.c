@@ -398,6 +398,12 @@ static void zone_rhs(const zone_t *z, const or_params *p, double rhs[ONF])
 
 int or_rhs(const or_mesh *m, const or_params *p, const double *u, double *rhs)
 {
+    return or_rhs_blocks(m, p, u, rhs, 0);
+}
+
+int or_rhs_blocks(const or_mesh *m, const or_params *p, const double *u, double *rhs,
+                  const int8_t *only)
+{
     stencils_t S;
     if (make_stencils(p->fd_order, &S)) return -1;
     int g = m->g;
@@ -405,6 +411,7 @@ int or_rhs(const or_mesh *m, const or_params *p, const double *u, double *rhs)
     int64_t roff = 0;
     for (int b = 0; b < m->nb; ++b) {
         int n = m->n[b];
+        if (only && !only[b]) { roff += (int64_t)ONF * n * n * n; continue; }
         blk_t B;
         B.E = n + 2 * g;
         B.u = u + or_block_offset(m, b);

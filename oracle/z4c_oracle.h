@@ -68,6 +68,9 @@ int or_fill_ghosts(const or_mesh *m, double *u);
 
 /* RHS of all interior zones; u must have ghosts filled. rhs: interior layout */
 int or_rhs(const or_mesh *m, const or_params *p, const double *u, double *rhs);
+/* same, only for blocks with only[b] != 0 (others left untouched) */
+int or_rhs_blocks(const or_mesh *m, const or_params *p, const double *u, double *rhs,
+                  const int8_t *only);
 
 /* one classic RK4 stage on registers U,S1,S2,A (ghosted layout, all FP64):
  * fills ghosts of the stage input itself. */

@@ -27,6 +27,12 @@ struct z4c_pack {
     std::vector<int32_t> map;
     LookupDev L;
     bool multilevel = false;
+    // cross-level fill tables
+    std::vector<XferItem> xfer;
+    std::vector<ProlongItem> prol;
+    std::vector<double> rw, pw, wtab;
+    int64_t shadow_elems = 0;
+    size_t ws_xfer = 0, ws_prol = 0, ws_w = 0, ws_shadow = 0;
     int maxghost = 0;
     int64_t zones = 0;
     size_t reg_bytes[Z4C_NREG] = {0, 0, 0, 0};
@@ -85,15 +91,195 @@ ParamsDev dev_params(const z4c_params& p)
     return d;
 }
 
-// tile shape of the fused stage kernel for an n^3 block (256 threads)
-void tile_shape(int n, int& ti, int& tj, int& tk)
+// tile shape of the fused stage kernel (256 threads, one zone each)
+void tile_shape(int, int& ti, int& tj, int& tk)
 {
-    ti = std::min(n, 32);
-    tj = std::min(n, std::max(1, 256 / ti));
-    tk = std::min(n, std::max(1, 256 / (ti * tj)));
+    ti = 8;
+    tj = 8;
+    tk = 4;
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int64_t fdiv(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// Lagrange weights (Eq. 1 of the paper) of the nodes q + 1/2, q = 0..n-1, at t
+void lagrange_half(int n, double t, double* w)
+{
+    for (int q = 0; q < n; ++q) {
+        double p = 1.0;
+        for (int m = 0; m < n; ++m)
+            if (m != q) p *= (t - (m + 0.5)) / ((q + 0.5) - (m + 0.5));
+        w[q] = p;
+    }
+}
+
+// Host-side queries on the block layout of a pack.
+struct Geo {
+    const z4c_pack* pk;
+    void bc(int l, int64_t I[3]) const
+    {
+        for (int a = 0; a < 3; ++a) {
+            const int64_t N = (int64_t)pk->p.nroot[a] << l;
+            if (pk->p.bc == Z4C_BC_PERIODIC) {
+                I[a] %= N;
+                if (I[a] < 0) I[a] += N;
+            } else {
+                I[a] = I[a] < 0 ? 0 : (I[a] >= N ? N - 1 : I[a]);
+            }
+        }
+    }
+    // leaf of exactly level l covering cell I (I inside the domain), or -1
+    int leaf(int l, const int64_t I[3]) const
+    {
+        if (l < 0 || l >= pk->L.nlev) return -1;
+        const int u = pk->L.unit;
+        int64_t q[3];
+        for (int a = 0; a < 3; ++a) {
+            q[a] = I[a] / u;
+            if (I[a] < 0 || q[a] >= pk->L.dim[l][a]) return -1;
+        }
+        return pk->map[pk->L.base[l] + (q[2] * pk->L.dim[l][1] + q[1]) * pk->L.dim[l][0] + q[0]];
+    }
+    int64_t cell(int b, const int64_t I[3]) const  // ghosted element offset of active cell I of block b
+    {
+        const BlockDev& B = pk->bdev[b];
+        const int g = pk->p.nghost;
+        return ((I[2] - B.ilo[2] + g) * (int64_t)B.E + (I[1] - B.ilo[1] + g)) * B.E + (I[0] - B.ilo[0] + g);
+    }
+    // restriction of coarse cell J (level l) from fine leaf F: window origin and weight sets
+    void restrict_window(int F, const int64_t J[3], int64_t& src, uint8_t d[3]) const
+    {
+        const int nr = pk->p.nghost + 1;
+        const z4c_block& FB = pk->blk[F];
+        int64_t s[3];
+        for (int a = 0; a < 3; ++a) {
+            const int64_t c = 2 * J[a];
+            int64_t st;
+            if (nr % 2 == 0) st = c - nr / 2 + 1;
+            else {
+                const double mid = FB.ilo[a] + 0.5 * FB.n;
+                st = ((double)(c + 1) < mid) ? c - (nr - 1) / 2 + 1 : c - (nr - 1) / 2;
+            }
+            const int64_t lo = FB.ilo[a], hi = FB.ilo[a] + FB.n - 1;
+            if (st < lo) st = lo;
+            if (st + nr - 1 > hi) st = hi - nr + 1;
+            s[a] = st;
+            d[a] = (uint8_t)(c + 1 - st);
+        }
+        src = pk->bdev[F].off + cell(F, s);
+    }
+};
+
+// Build the transfer / prolongation lists of a multi-level pack.
+int build_xlevel(z4c_pack* pk)
+{
+    const int g = pk->p.nghost, np = g + 1;
+    if (np > 8) return Z4C_EUNSUPPORTED;
+    Geo geo{pk};
+    pk->rw.assign(64, 0.0);
+    pk->pw.assign(16, 0.0);
+    for (int d = 1; d < np; ++d) lagrange_half(np, (double)d, &pk->rw[8 * d]);
+    {
+        const double t0 = (np % 2 == 0) ? np / 2 + 0.25 : (np - 1) / 2 + 0.25;
+        const double t1 = (np % 2 == 0) ? np / 2 - 0.25 : (np - 1) / 2 + 0.75;
+        lagrange_half(np, t0, &pk->pw[0]);
+        lagrange_half(np, t1, &pk->pw[8]);
+    }
+    const size_t esz = pk->p.precision == Z4C_FP64 ? 8 : 4;
+    const int64_t per256 = 256 / (int64_t)esz;
+    const int nb = (int)pk->blk.size();
+    for (int b = 0; b < nb; ++b) {
+        const z4c_block& B = pk->blk[b];
+        const BlockDev& D = pk->bdev[b];
+        const int l = B.level, n = B.n, E = D.E;
+        // shadow box of this block at level l-1 (allocated on first use)
+        int64_t S0[3];
+        const int64_t SE = (n + 2 * g) / 2 + 2 * (np + 1) + 2;
+        for (int a = 0; a < 3; ++a) S0[a] = fdiv(B.ilo[a] - g, 2) - (np + 1);
+        int64_t shoff = -1;
+        std::vector<uint8_t> mark;
+        for (int k = 0; k < E; ++k)
+            for (int j = 0; j < E; ++j)
+                for (int i = 0; i < E; ++i) {
+                    if (i >= g && i < g + n && j >= g && j < g + n && k >= g && k < g + n) continue;
+                    const int64_t G[3] = {B.ilo[0] + i - g, B.ilo[1] + j - g, B.ilo[2] + k - g};
+                    int64_t Gb[3] = {G[0], G[1], G[2]};
+                    geo.bc(l, Gb);
+                    if (geo.leaf(l, Gb) >= 0) continue;  // same level
+                    const int64_t dcell = D.off + ((int64_t)k * E + j) * E + i;
+                    const int64_t C2[3] = {2 * Gb[0], 2 * Gb[1], 2 * Gb[2]};
+                    const int F = geo.leaf(l + 1, C2);
+                    if (F >= 0) {
+                        XferItem it;
+                        it.dst = dcell;
+                        it.dst_stride = D.slab;
+                        geo.restrict_window(F, Gb, it.src, it.d);
+                        it.src_block = F;
+                        it.kind = 1;
+                        pk->xfer.push_back(it);
+                        continue;
+                    }
+                    const int64_t P[3] = {Gb[0] / 2, Gb[1] / 2, Gb[2] / 2};
+                    if (geo.leaf(l - 1, P) < 0) return Z4C_EINVAL;
+                    // prolongation: stencil around the periodic-unwrapped or clamped index
+                    const int64_t* Iu = (pk->p.bc == Z4C_BC_PERIODIC) ? G : Gb;
+                    int64_t s[3];
+                    int parity = 0;
+                    for (int a = 0; a < 3; ++a) {
+                        const int64_t J = fdiv(Iu[a], 2);
+                        const int odd = (int)(Iu[a] - 2 * J);
+                        parity |= odd << a;
+                        s[a] = (np % 2) ? J - (np - 1) / 2 : (odd ? J - np / 2 + 1 : J - np / 2);
+                        if (s[a] < S0[a] || s[a] + np > S0[a] + SE) return Z4C_EINVAL;
+                    }
+                    if (shoff < 0) {
+                        shoff = pk->shadow_elems;
+                        const int64_t cells = SE * SE * SE;
+                        pk->shadow_elems += NF * ((cells + per256 - 1) / per256 * per256);
+                        mark.assign((size_t)(SE * SE * SE), 0);
+                    }
+                    const int64_t fstride = (SE * SE * SE + per256 - 1) / per256 * per256;
+                    for (int kz = 0; kz < np; ++kz)
+                        for (int jy = 0; jy < np; ++jy)
+                            for (int ix = 0; ix < np; ++ix) {
+                                const int64_t K[3] = {s[0] + ix, s[1] + jy, s[2] + kz};
+                                const int64_t loc = ((K[2] - S0[2]) * SE + (K[1] - S0[1])) * SE + (K[0] - S0[0]);
+                                if (mark[loc]) continue;
+                                mark[loc] = 1;
+                                int64_t Kb[3] = {K[0], K[1], K[2]};
+                                geo.bc(l - 1, Kb);
+                                XferItem it;
+                                it.dst = shoff + loc;
+                                it.dst_stride = fstride;
+                                it.kind = 2;
+                                it.d[0] = it.d[1] = it.d[2] = 0;
+                                const int Cb = geo.leaf(l - 1, Kb);
+                                if (Cb >= 0) {
+                                    it.src = pk->bdev[Cb].off + geo.cell(Cb, Kb);
+                                    it.src_block = Cb;
+                                } else {
+                                    const int64_t K2[3] = {2 * Kb[0], 2 * Kb[1], 2 * Kb[2]};
+                                    const int Fb = geo.leaf(l, K2);
+                                    if (Fb < 0) return Z4C_EINVAL;  // would need a level two away
+                                    geo.restrict_window(Fb, Kb, it.src, it.d);
+                                    it.src_block = Fb;
+                                    it.kind = 3;
+                                }
+                                pk->xfer.push_back(it);
+                            }
+                    ProlongItem pi;
+                    pi.dst = dcell;
+                    pi.sh = shoff + ((s[2] - S0[2]) * SE + (s[1] - S0[1])) * SE + (s[0] - S0[0]);
+                    pi.block = b;
+                    pi.se = (int32_t)SE;
+                    pi.parity = parity;
+                    pi.pad = (int32_t)fstride;  // field stride of the shadow box
+                    pk->prol.push_back(pi);
+                }
+    }
+    return Z4C_OK;
+}
 
 // bracket a launch with events when profiling is on (kind 0 stage, 1 fill)
 struct ProfScope {
@@ -145,7 +331,8 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
     int lmax = 0, unit = 0;
     for (int b = 0; b < nblocks; ++b) {
         const z4c_block& B = blocks[b];
-        if (B.level < 0 || B.level > 7 || B.n < 2 || (B.n % 2) || B.n < g || B.n > 512) {
+        // the stage kernel works on 8 x 8 x 4 tiles of active cells
+        if (B.level < 0 || B.level > 7 || B.n < 8 || (B.n % 8) || B.n < g || B.n > 512) {
             delete pk;
             return Z4C_EINVAL;
         }
@@ -266,12 +453,21 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
                 }
     }
 
+    if (pk->multilevel) {
+        const int rc = build_xlevel(pk);
+        if (rc) { delete pk; return rc; }
+    }
+
     // workspace
     size_t o = 0;
     pk->ws_blocks = o; o = align256(o + sizeof(BlockDev) * nblocks);
     pk->ws_work = o;   o = align256(o + sizeof(WorkItem) * pk->work.size());
     pk->ws_map = o;    o = align256(o + sizeof(int32_t) * pk->map.size());
     pk->ws_part = o;   o = align256(o + sizeof(double) * 8 * pk->work.size());
+    pk->ws_xfer = o;   o = align256(o + sizeof(XferItem) * pk->xfer.size());
+    pk->ws_prol = o;   o = align256(o + sizeof(ProlongItem) * pk->prol.size());
+    pk->ws_w = o;      o = align256(o + sizeof(double) * 80);
+    pk->ws_shadow = o; o = align256(o + esz * (size_t)pk->shadow_elems);
     pk->ws_total = o;
     pk->part_host.resize(8 * pk->work.size());
     *out = pk;
@@ -319,6 +515,19 @@ int z4c_pack_bind(z4c_pack* pk, void* const regs[Z4C_NREG], void* workspace, siz
     if (e == hipSuccess)
         e = hipMemcpyAsync(ws + pk->ws_map, pk->map.data(), sizeof(int32_t) * pk->map.size(),
                            hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !pk->xfer.empty())
+        e = hipMemcpyAsync(ws + pk->ws_xfer, pk->xfer.data(), sizeof(XferItem) * pk->xfer.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !pk->prol.empty())
+        e = hipMemcpyAsync(ws + pk->ws_prol, pk->prol.data(), sizeof(ProlongItem) * pk->prol.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && pk->multilevel) {
+        double wt[80];
+        for (int q = 0; q < 64; ++q) wt[q] = pk->rw[q];
+        for (int q = 0; q < 16; ++q) wt[64 + q] = pk->pw[q];
+        pk->wtab.assign(wt, wt + 80);
+        e = hipMemcpyAsync(ws + pk->ws_w, pk->wtab.data(), sizeof(double) * 80, hipMemcpyHostToDevice, s);
+    }
     if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "table upload: %s", hipGetErrorString(e));
     for (int r = 0; r < Z4C_NREG; ++r) pk->reg[r] = regs[r];
     pk->ws = ws;
@@ -372,7 +581,6 @@ int z4c_fill_ghosts(z4c_pack* pk, int32_t reg, void* stream)
     if (reg < Z4C_REG_U || reg > Z4C_REG_S2) return fail(pk, Z4C_EINVAL, "bad register %d", reg);
     if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
     if (pk->p.bc == Z4C_BC_USER) return Z4C_OK;
-    if (pk->multilevel) return fail(pk, Z4C_EUNSUPPORTED, "cross-level ghost fill not built");
     FillArgs a;
     a.reg = pk->reg[reg];
     a.blocks = reinterpret_cast<const BlockDev*>(pk->ws + pk->ws_blocks);
@@ -384,6 +592,20 @@ int z4c_fill_ghosts(z4c_pack* pk, int32_t reg, void* stream)
     a.maxghost = pk->maxghost;
     ProfScope ps(pk, as_stream(stream), 1);
     hipError_t e = launch_fill(pk->p.precision, a, (int)pk->blk.size(), as_stream(stream));
+    if (e == hipSuccess && pk->multilevel) {
+        XlevelArgs x;
+        x.reg = pk->reg[reg];
+        x.shadow = pk->ws + pk->ws_shadow;
+        x.blocks = a.blocks;
+        x.xfer = reinterpret_cast<const XferItem*>(pk->ws + pk->ws_xfer);
+        x.prol = reinterpret_cast<const ProlongItem*>(pk->ws + pk->ws_prol);
+        x.rw = reinterpret_cast<const double*>(pk->ws + pk->ws_w);
+        x.pw = x.rw + 64;
+        x.nxfer = (int64_t)pk->xfer.size();
+        x.nprol = (int64_t)pk->prol.size();
+        x.npts = pk->p.nghost + 1;
+        e = launch_xlevel(pk->p.precision, x, as_stream(stream));
+    }
     if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "ghost fill launch: %s", hipGetErrorString(e));
     return Z4C_OK;
 }

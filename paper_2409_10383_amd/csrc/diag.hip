@@ -38,12 +38,12 @@ __global__ __launch_bounds__(256) void k_constraints(const DiagArgs a)
     const bool live = lk < w.nk;
     const int i = w.i0 + li, j = w.j0 + lj, k = w.k0 + lk;
     const int g = a.g, E = B.E, n = B.n;
-    double c[NF], v[NF];
+    double c[8];
     double H = 0, M2 = 0, T2 = 0, G2 = 0, dv = 0;
     if (live) {
         const int64_t cc = ((int64_t)(k + g) * E + (j + g)) * E + (i + g);
         const T* src = (const T*)a.src + B.off + cc;
-        zone_rhs<N, T, double, true>(src, B.slab, E, E * E, 1.0 / B.h, a.P, c, v);
+        zone_constraints<N, T>(src, B.slab, E, E * E, 1.0 / B.h, a.P, c);
         if (a.per_zone) {
             const int64_t n3 = (int64_t)n * n * n;
             const int64_t ci = (B.ioff / NF) * 8 + ((int64_t)k * n + j) * n + i;

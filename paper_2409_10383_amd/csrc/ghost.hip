@@ -79,6 +79,87 @@ __global__ __launch_bounds__(256) void k_fill_same(const FillArgs a)
     for (int f = 0; f < NF; ++f) r[d + f * B.slab] = r[so + f * SB.slab];
 }
 
+// copies and restrictions (reads active cells only)
+template <class T>
+__global__ __launch_bounds__(256) void k_xfer(const XlevelArgs a)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.nxfer) return;
+    const XferItem it = a.xfer[q];
+    const BlockDev S = a.blocks[it.src_block];
+    const T* __restrict__ src = (const T*)a.reg + it.src;
+    T* dst = (T*)((it.kind & 2) ? a.shadow : a.reg) + it.dst;
+    const int np = a.npts;
+    if (!(it.kind & 1)) {
+        for (int f = 0; f < NF; ++f) dst[f * it.dst_stride] = src[f * S.slab];
+        return;
+    }
+    const double* wx = a.rw + 8 * it.d[0];
+    const double* wy = a.rw + 8 * it.d[1];
+    const double* wz = a.rw + 8 * it.d[2];
+    const int64_t E = S.E;
+    for (int f = 0; f < NF; ++f) {
+        const T* p = src + f * S.slab;
+        double acc = 0.0;
+        for (int kz = 0; kz < np; ++kz) {
+            double az = 0.0;
+            for (int jy = 0; jy < np; ++jy) {
+                const T* row = p + (kz * E + jy) * E;
+                double ay = 0.0;
+                for (int ix = 0; ix < np; ++ix) ay += wx[ix] * (double)row[ix];
+                az += wy[jy] * ay;
+            }
+            acc += wz[kz] * az;
+        }
+        dst[f * it.dst_stride] = (T)acc;
+    }
+}
+
+// prolongation of fine ghosts from the shadow boxes
+template <class T>
+__global__ __launch_bounds__(256) void k_prolong(const XlevelArgs a)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.nprol) return;
+    const ProlongItem it = a.prol[q];
+    const BlockDev B = a.blocks[it.block];
+    const T* __restrict__ sh = (const T*)a.shadow + it.sh;
+    T* dst = (T*)a.reg + it.dst;
+    const int np = a.npts;
+    const int64_t se = it.se, se3 = it.pad;  // field stride of the shadow box
+    const double* wx = a.pw + 8 * (it.parity & 1);
+    const double* wy = a.pw + 8 * ((it.parity >> 1) & 1);
+    const double* wz = a.pw + 8 * ((it.parity >> 2) & 1);
+    for (int f = 0; f < NF; ++f) {
+        const T* p = sh + f * se3;
+        double acc = 0.0;
+        for (int kz = 0; kz < np; ++kz) {
+            double az = 0.0;
+            for (int jy = 0; jy < np; ++jy) {
+                const T* row = p + (kz * se + jy) * se;
+                double ay = 0.0;
+                for (int ix = 0; ix < np; ++ix) ay += wx[ix] * (double)row[ix];
+                az += wy[jy] * ay;
+            }
+            acc += wz[kz] * az;
+        }
+        dst[f * B.slab] = (T)acc;
+    }
+}
+
+hipError_t launch_xlevel(int prec, const XlevelArgs& a, hipStream_t s)
+{
+    const unsigned gx = (unsigned)((a.nxfer + 255) / 256), gp = (unsigned)((a.nprol + 255) / 256);
+    if (prec == 0) {
+        if (gx) hipLaunchKernelGGL(k_xfer<double>, dim3(gx), dim3(256), 0, s, a);
+        if (gp) hipLaunchKernelGGL(k_prolong<double>, dim3(gp), dim3(256), 0, s, a);
+    } else {
+        if (gx) hipLaunchKernelGGL(k_xfer<float>, dim3(gx), dim3(256), 0, s, a);
+        if (gp) hipLaunchKernelGGL(k_prolong<float>, dim3(gp), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(int prec, const FillArgs& a, int nblocks, hipStream_t s)
 {
     dim3 grid((unsigned)((a.maxghost + 255) / 256), (unsigned)nblocks);

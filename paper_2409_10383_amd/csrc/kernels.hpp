@@ -29,6 +29,18 @@ struct FillArgs {
     int32_t maxghost;         // ghost cells of the largest block
 };
 
+struct XlevelArgs {
+    void* reg;                // register being filled
+    void* shadow;             // shadow boxes (same element type)
+    const BlockDev* blocks;
+    const XferItem* xfer;
+    const ProlongItem* prol;
+    const double* rw;         // restriction weights [8][8]: set d, point q
+    const double* pw;         // prolongation weights [2][8]: parity, point q
+    int64_t nxfer, nprol;
+    int32_t npts;             // g + 1
+};
+
 struct DiagArgs {
     const void* src;
     double* per_zone;         // nullable
@@ -47,5 +59,6 @@ struct DiagArgs {
 hipError_t launch_stage(int N, int prec, const StageArgs& a, int nwork, hipStream_t s);
 hipError_t launch_fill(int prec, const FillArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_diag(int N, int prec, const DiagArgs& a, int nwork, hipStream_t s);
+hipError_t launch_xlevel(int prec, const XlevelArgs& a, hipStream_t s);
 
 }  // namespace z4c

@@ -1,25 +1,314 @@
-// Fused Z4c RHS + classic RK4 stage kernel (one launch per stage covers the
-// whole MeshBlockPack; work items are tiles of active cells).
+// Fused Z4c RHS + classic RK4 stage kernel.
+//
+// One launch per RK stage covers the whole MeshBlockPack: each workgroup
+// (256 threads, one zone each) owns an 8 x 8 x 4 tile of active cells of
+// one MeshBlock and streams the 22 fields through LDS one at a time: the
+// field's tile plus an (N+1)-cell halo is staged (coalesced, x fastest),
+// then every derivative the method needs of that field is taken from LDS:
+//   - per axis, one pass over the 2(N+1) neighbours gives the centred first
+//     and second derivatives, the odd (advective) and even (advective +
+//     Kreiss-Oliger) parts of the upwind-biased operator;
+//   - mixed second derivatives in two passes, d_x f then d_y(d_x f),
+//     d_z(d_x f), d_z(d_y f), through LDS intermediates;
+//   - second derivatives are contracted into the Ricci tensor and the shift
+//     terms as soon as they are produced, so only first derivatives and a
+//     few accumulators stay live in registers.
+// The per-zone algebra then builds the 22 RHS values (equations listed in
+// z4c_rhs.hpp), the RK4 update runs in double against the FP64 accumulator,
+// and the algebraic constraints and floors are applied before the store.
 #include "kernels.hpp"
 #include "z4c_rhs.hpp"
 
 namespace z4c {
 
+constexpr int TX = 8, TY = 8, TZ = 4;
+
+template <int N> struct TileGeom {
+    static constexpr int R = N + 1;                 // halo of the staged tile
+    static constexpr int SX = TX + 2 * R, SY = TY + 2 * R, SZ = TZ + 2 * R;
+    static constexpr int NS = SX * SY * SZ;         // staged cells
+    static constexpr int DXY = TY + 2 * N, DXZ = TZ + 2 * N;
+    static constexpr int NDX = TX * DXY * DXZ;      // d_x f on y, z halos
+    static constexpr int NDY = TX * TY * DXZ;       // d_y f on a z halo
+};
+
+// one axis of a staged field: centred d1, d2 (both optional) and the
+// advection + dissipation contribution; no 1/h factors
+// va is the advection speed along the axis (0 when advection is off) and
+// sig the dissipation strength: ad += va*odd + |va|*even_lop + sig*even_ko
+template <int N, class C, bool D1, bool D2>
+__device__ __forceinline__ void axis_pass(const C* __restrict__ s, int c, int st, C va, C sig,
+                                          C& d1, C& d2, C& ad)
+{
+    const C f0 = s[c];
+    C a1 = 0, a2 = 0, odd = 0, el = 0, ek = 0;
+#pragma unroll
+    for (int k = 1; k <= N + 1; ++k) {
+        const C fp = s[c + k * st], fm = s[c - k * st];
+        const C dk = fp - fm;
+        const C sk = (fp - f0) + (fm - f0);
+        if (k <= N) {
+            if (D1) a1 += (C)Stencil<N>::D1[k] * dk;
+            if (D2) a2 += (C)Stencil<N>::D2[k] * sk;
+        }
+        odd += (C)lop_odd<N>(k) * dk;
+        el += (C)lop_even<N>(k) * sk;
+        ek += (C)Stencil<N>::KO[k] * sk;
+    }
+    d1 = a1;
+    d2 = a2;
+    ad += va * odd + (C)fabs((double)va) * el + sig * ek;
+}
+
 template <int N, class T, class C>
 __global__ __launch_bounds__(256) void k_stage(const StageArgs a)
 {
+    using G = TileGeom<N>;
+    constexpr int R = G::R, SX = G::SX, SY = G::SY;
+    __shared__ C tile[G::NS];
+    __shared__ C dxs[G::NDX];
+    __shared__ C dys[G::NDY];
+    __shared__ C adks[NF * 256];   // advection + dissipation, per field and zone
+
     const WorkItem w = a.work[blockIdx.x];
     const BlockDev B = a.blocks[w.block];
     const int t = threadIdx.x;
-    const int li = t % w.ni, lj = (t / w.ni) % w.nj, lk = t / (w.ni * w.nj);
-    if (lk >= w.nk) return;
-    const int i = w.i0 + li, j = w.j0 + lj, k = w.k0 + lk;
+    const int tx = t & 7, ty = (t >> 3) & 7, tz = t >> 6;
+    const int i = w.i0 + tx, j = w.j0 + ty, k = w.k0 + tz;
     const int g = a.g, E = B.E, n = B.n;
-    const int64_t c = ((int64_t)(k + g) * E + (j + g)) * E + (i + g);
-    const T* __restrict__ src = (const T*)a.src + B.off + c;
-    C rhs[NF], v[NF];
-    zone_rhs<N, T, C>(src, B.slab, E, E * E, (C)(1.0 / B.h), a.P, rhs, v);
+    const int64_t slab = B.slab;
+    const T* __restrict__ srcb = (const T*)a.src + B.off;
+    const int64_t cz = ((int64_t)(k + g) * E + (j + g)) * E + (i + g);  // zone, ghosted index
+    const C ih = (C)(1.0 / B.h), ih2 = ih * ih;
+    const ParamsDev& P = a.P;
 
+    // staged-tile index of this zone and its strides
+    const int c = ((tz + R) * SY + (ty + R)) * SX + (tx + R);
+    const int sxy = SX * SY;
+
+    // stage field f (tile + halo R) into LDS
+    const int64_t base0 = ((int64_t)(w.k0 - R + g) * E + (w.j0 - R + g)) * E + (w.i0 - R + g);
+    auto stage = [&](int f) {
+        const T* __restrict__ p = srcb + f * slab + base0;
+        for (int q = t; q < G::NS; q += 256) {
+            const int x = q % SX, y = (q / SX) % SY, z = q / sxy;
+            tile[q] = (C)p[((int64_t)z * E + y) * E + x];
+        }
+    };
+    // d_x f on the y/z halo and d_y f on the z halo (for mixed derivatives)
+    auto first_pass = [&]() {
+        for (int q = t; q < G::NDX; q += 256) {
+            const int x = q % TX, y = (q / TX) % G::DXY, z = q / (TX * G::DXY);
+            const int cc = ((z + R - N) * SY + (y + R - N)) * SX + (x + R);
+            dxs[q] = fd1<N, C>(tile + cc, 1);
+        }
+        for (int q = t; q < G::NDY; q += 256) {
+            const int x = q % TX, y = (q / TX) % TY, z = q / (TX * TY);
+            const int cc = ((z + R - N) * SY + (y + R)) * SX + (x + R);
+            dys[q] = fd1<N, C>(tile + cc, SX);
+        }
+    };
+    // mixed derivatives of the staged field at this zone: xy, xz, yz
+    auto mixed = [&](C& mxy, C& mxz, C& myz) {
+        const int cx = ((tz + N) * G::DXY + (ty + N)) * TX + tx;
+        const int cy = ((tz + N) * TY + ty) * TX + tx;
+        mxy = fd1<N, C>(dxs + cx, TX);
+        mxz = fd1<N, C>(dxs + cx, TX * G::DXY);
+        myz = fd1<N, C>(dys + cy, TX * TY);
+    };
+
+    // ---- centre values needed before the sweep: shift, conformal metric
+    C be[3], gdn[6], gu[6];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) be[q] = (C)srcb[(F_BETAX + q) * slab + cz];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) gdn[q] = (C)srcb[(F_GXX + q) * slab + cz];
+    {
+        const C c0 = gdn[3] * gdn[5] - gdn[4] * gdn[4];
+        const C c1 = gdn[2] * gdn[4] - gdn[1] * gdn[5];
+        const C c2 = gdn[1] * gdn[4] - gdn[2] * gdn[3];
+        const C id = (C)1 / (gdn[0] * c0 + gdn[1] * c1 + gdn[2] * c2);
+        gu[0] = c0 * id; gu[1] = c1 * id; gu[2] = c2 * id;
+        gu[3] = (gdn[0] * gdn[5] - gdn[2] * gdn[2]) * id;
+        gu[4] = (gdn[1] * gdn[2] - gdn[0] * gdn[4]) * id;
+        gu[5] = (gdn[0] * gdn[3] - gdn[1] * gdn[1]) * id;
+    }
+    const bool adv = (P.terms & 4u) != 0;
+    const bool adv_gauge = adv && (P.terms & 2u);
+    const C sig = (P.terms & 8u) ? (C)P.ko_sigma : (C)0;
+    const int st3[3] = {1, SX, sxy};
+
+    C dg[3][6], Rt[6];   // d_a g~_p ; Ricci accumulator
+    C dchi[3], ddchi[6], dal[3], ddal[6], dbe[3][3], Lb[3], Bj[3], eK[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) { Lb[q] = 0; Bj[q] = 0; eK[q] = 0; }
+
+    // generic per-field sweep: first derivatives d1[3], pure second d2[3]
+    // advection + dissipation of field f at this zone, kept in LDS
+    auto put_adk = [&](int f, C v) { adks[f * 256 + t] = v; };
+    auto sweep = [&](int f, bool gauge_field, C* d1, C* d2, auto D1tag, auto D2tag) {
+        constexpr bool WD1 = decltype(D1tag)::value, WD2 = decltype(D2tag)::value;
+        const bool a_on = gauge_field ? adv_gauge : adv;
+        C ad = 0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            C x1, x2;
+            axis_pass<N, C, WD1, WD2>(tile, c, st3[d], a_on ? be[d] : (C)0, sig, x1, x2, ad);
+            if (WD1) d1[d] = x1 * ih;
+            if (WD2) d2[d] = x2 * ih2;
+        }
+        put_adk(f, ad * ih);
+    };
+    using T1 = std::integral_constant<bool, true>;
+    using F0 = std::integral_constant<bool, false>;
+
+    // ---- conformal metric: first derivatives, Ricci second-derivative term
+#pragma unroll 1
+    for (int p = 0; p < 6; ++p) {
+        __syncthreads();
+        stage(F_GXX + p);
+        __syncthreads();
+        first_pass();
+        __syncthreads();
+        C d1[3], d2[3], mxy, mxz, myz;
+        sweep(F_GXX + p, false, d1, d2, T1(), T1());
+        mixed(mxy, mxz, myz);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            // store d_d g~_p (p is a runtime loop index: select)
+#pragma unroll
+            for (int pp = 0; pp < 6; ++pp)
+                if (pp == p) dg[d][pp] = d1[d];
+        }
+        const C r = -(C)0.5 * (gu[0] * d2[0] + gu[3] * d2[1] + gu[5] * d2[2] +
+                               (C)2 * ih2 * (gu[1] * mxy + gu[2] * mxz + gu[4] * myz));
+#pragma unroll
+        for (int pp = 0; pp < 6; ++pp)
+            if (pp == p) Rt[pp] = r;
+    }
+    // ---- chi and alpha: first and second derivatives
+    {
+        __syncthreads();
+        stage(F_CHI);
+        __syncthreads();
+        first_pass();
+        __syncthreads();
+        C d2[3], mxy, mxz, myz;
+        sweep(F_CHI, false, dchi, d2, T1(), T1());
+        mixed(mxy, mxz, myz);
+        ddchi[0] = d2[0]; ddchi[3] = d2[1]; ddchi[5] = d2[2];
+        ddchi[1] = mxy * ih2; ddchi[2] = mxz * ih2; ddchi[4] = myz * ih2;
+    }
+    {
+        __syncthreads();
+        stage(F_ALPHA);
+        __syncthreads();
+        first_pass();
+        __syncthreads();
+        C d2[3], mxy, mxz, myz;
+        sweep(F_ALPHA, true, dal, d2, T1(), T1());
+        mixed(mxy, mxz, myz);
+        ddal[0] = d2[0]; ddal[3] = d2[1]; ddal[5] = d2[2];
+        ddal[1] = mxy * ih2; ddal[2] = mxz * ih2; ddal[4] = myz * ih2;
+    }
+    // ---- shift: first derivatives, g~^jk d_j d_k beta^i and d_j d_k beta^k
+#pragma unroll 1
+    for (int q = 0; q < 3; ++q) {
+        __syncthreads();
+        stage(F_BETAX + q);
+        __syncthreads();
+        first_pass();
+        __syncthreads();
+        C d1[3], d2[3], mxy, mxz, myz;
+        sweep(F_BETAX + q, true, d1, d2, T1(), T1());
+        mixed(mxy, mxz, myz);
+        mxy *= ih2; mxz *= ih2; myz *= ih2;
+        const C dd[6] = {d2[0], mxy, mxz, d2[1], myz, d2[2]};
+        const C lb = gu[0] * dd[0] + gu[3] * dd[3] + gu[5] * dd[5] +
+                     (C)2 * (gu[1] * dd[1] + gu[2] * dd[2] + gu[4] * dd[4]);
+#pragma unroll
+        for (int qq = 0; qq < 3; ++qq)
+            if (qq == q) {
+                Lb[qq] = lb;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) dbe[d][qq] = d1[d];
+                // B_j += d_j d_q beta^q
+                Bj[0] += dd[S(0, qq)];
+                Bj[1] += dd[S(1, qq)];
+                Bj[2] += dd[S(2, qq)];
+            }
+    }
+    // ---- Gamma~: its first derivatives enter R~_ij only
+#pragma unroll 1
+    for (int q = 0; q < 3; ++q) {
+        __syncthreads();
+        stage(F_GAMX + q);
+        __syncthreads();
+        C d1[3], d2[3];
+        sweep(F_GAMX + q, false, d1, d2, T1(), F0());
+        // R~_ij += 1/2 (g~_qi d_j G^q + g~_qj d_i G^q)
+#pragma unroll
+        for (int qq = 0; qq < 3; ++qq)
+            if (qq == q) {
+#pragma unroll
+                for (int pp = 0; pp < 6; ++pp) {
+                    const int ii = SA(pp), jj = SB(pp);
+                    Rt[pp] += (C)0.5 * (gdn[S(qq, ii)] * d1[jj] + gdn[S(qq, jj)] * d1[ii]);
+                }
+            }
+    }
+    // ---- Khat and Theta: 2 d Khat + d Theta
+    {
+        __syncthreads();
+        stage(F_KH);
+        __syncthreads();
+        C d1[3], d2[3];
+        sweep(F_KH, false, d1, d2, T1(), F0());
+#pragma unroll
+        for (int d = 0; d < 3; ++d) eK[d] = (C)2 * d1[d];
+        __syncthreads();
+        stage(F_TH);
+        __syncthreads();
+        sweep(F_TH, false, d1, d2, T1(), F0());
+#pragma unroll
+        for (int d = 0; d < 3; ++d) eK[d] += d1[d];
+    }
+    // ---- A~_ij: advection and dissipation only
+#pragma unroll 1
+    for (int p = 0; p < 6; ++p) {
+        __syncthreads();
+        stage(F_AXX + p);
+        __syncthreads();
+        C d1[3], d2[3], ad;
+        {
+            const bool a_on = adv;
+            ad = 0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                C x1, x2;
+                axis_pass<N, C, false, false>(tile, c, st3[d], a_on ? be[d] : (C)0, sig, x1, x2, ad);
+            }
+        }
+        (void)d1; (void)d2;
+        put_adk(F_AXX + p, ad * ih);
+    }
+
+    // ---- centre values and the per-zone algebra
+    const C chi = (C)srcb[F_CHI * slab + cz], Kh = (C)srcb[F_KH * slab + cz];
+    const C Th = (C)srcb[F_TH * slab + cz], al = (C)srcb[F_ALPHA * slab + cz];
+    C A[6], Gam[3];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) A[q] = (C)srcb[(F_AXX + q) * slab + cz];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) Gam[q] = (C)srcb[(F_GAMX + q) * slab + cz];
+
+    C rhs[NF];
+    z4c_algebra<C>(P, chi, gdn, gu, Kh, A, Gam, Th, al, be, dg, dchi, ddchi, dal, ddal, dbe, Lb,
+                   Bj, eK, Rt, rhs);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) rhs[f] += adks[f * 256 + t];
+
+    // ---- RK4 stage update
     const int64_t n3 = (int64_t)n * n * n;
     const int64_t ci = B.ioff + ((int64_t)k * n + j) * n + i;
     if (a.stage == 0) {
@@ -29,24 +318,24 @@ __global__ __launch_bounds__(256) void k_stage(const StageArgs a)
     }
     const double dt = a.dt;
     double out[NF];
-    const T* __restrict__ U = (const T*)a.U + B.off + c;
+    const T* __restrict__ U = (const T*)a.U + B.off + cz;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         const double kf = (double)rhs[f];
         double* Af = a.A + ci + f * n3;
         switch (a.stage) {
         case 1: {
-            const double u = (double)v[f];
+            const double u = (double)U[f * slab];
             out[f] = u + 0.5 * dt * kf;
             *Af = u + dt / 6.0 * kf;
         } break;
         case 2: {
-            const double u = (double)U[f * B.slab];
+            const double u = (double)U[f * slab];
             out[f] = u + 0.5 * dt * kf;
             *Af += dt / 3.0 * kf;
         } break;
         case 3: {
-            const double u = (double)U[f * B.slab];
+            const double u = (double)U[f * slab];
             out[f] = u + dt * kf;
             *Af += dt / 3.0 * kf;
         } break;
@@ -54,10 +343,10 @@ __global__ __launch_bounds__(256) void k_stage(const StageArgs a)
             out[f] = *Af + dt / 6.0 * kf;
         }
     }
-    if (a.P.enforce) enforce_zone(out, a.P);
-    T* __restrict__ dst = (T*)a.dst + B.off + c;
+    if (P.enforce) enforce_zone(out, P);
+    T* __restrict__ dst = (T*)a.dst + B.off + cz;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) dst[f * B.slab] = (T)out[f];
+    for (int f = 0; f < NF; ++f) dst[f * slab] = (T)out[f];
 }
 
 template <int N>

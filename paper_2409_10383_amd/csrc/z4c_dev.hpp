@@ -43,6 +43,29 @@ struct LookupDev {
     int64_t base[8];      // per level: start in `map`
 };
 
+// cross-level ghost fill (refinement boundaries)
+// A transfer writes 22 values: a copy of one active cell, or the Lagrange
+// restriction (n = g+1 points per axis) of a window of fine active cells,
+// into a ghost cell of a register or into a block's coarse shadow box.
+struct XferItem {
+    int64_t dst;          // element offset of field 0 at the destination
+    int64_t dst_stride;   // element stride between fields at the destination
+    int64_t src;          // element offset (field 0) of the source cell / window origin
+    int32_t src_block;    // source block (field stride and row length)
+    uint8_t kind;         // bit0: restriction (else copy); bit1: destination is a shadow box
+    uint8_t d[3];         // per-axis restriction weight set
+};
+// A prolongation fills one fine ghost cell from the (g+1)^3 coarse values
+// of its block's shadow box.
+struct ProlongItem {
+    int64_t dst;          // register element offset of field 0
+    int64_t sh;           // shadow element offset of the stencil origin (field 0)
+    int32_t block;        // destination block (field stride)
+    int32_t se;           // shadow box extent per axis
+    int32_t parity;       // bit a: fine index along axis a is odd
+    int32_t pad;          // field stride of the shadow box (elements)
+};
+
 // physics / method parameters as the kernels read them
 struct ParamsDev {
     double ko_sigma, kappa1, kappa2, eta, mu_S, chi_floor, alpha_floor;

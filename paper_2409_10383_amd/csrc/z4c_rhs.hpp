@@ -76,21 +76,6 @@ __device__ __forceinline__ C fdmix(const T* __restrict__ p, int sa, int sb)
     return acc;
 }
 
-// advection + dissipation along one axis: v*odd + sum_k ev[k] * (pair sums)
-template <int N, class C, class T>
-__device__ __forceinline__ C fadvdiss(const T* __restrict__ p, int s, C v, const C* ev)
-{
-    const C f0 = (C)p[0];
-    C odd = 0, even = 0;
-#pragma unroll
-    for (int k = 1; k <= N + 1; ++k) {
-        const C fp = (C)p[k * s], fm = (C)p[-k * s];
-        odd += (C)lop_odd<N>(k) * (fp - fm);
-        even += ev[k] * ((fp - f0) + (fm - f0));
-    }
-    return v * odd + even;
-}
-
 // division by chi is done in double whatever C is
 template <class C> __device__ __forceinline__ C inv_chi(C chi, double floor_)
 {
@@ -99,65 +84,12 @@ template <class C> __device__ __forceinline__ C inv_chi(C chi, double floor_)
     return (C)(1.0 / c);
 }
 
-// The RHS of one zone.  `z` points at field 0 of the zone in a ghosted
-// state register; fields are `slab` elements apart; sy, sz the row and
-// plane strides.  Returns the 22 centre values in v and the RHS in rhs.
-template <int N, class T, class C, bool CONS = false>
-__device__ __forceinline__ void zone_rhs(const T* __restrict__ z, int64_t slab, int sy, int sz,
-                                         C ih, const ParamsDev& P, C* __restrict__ rhs,
-                                         C* __restrict__ v)
+// Christoffel symbols from d_a g~_p: Gl[k][ij] = G~_kij, Gu[k][ij] = G~^k_ij,
+// and the contracted G~d^i = g~^jk G~^i_jk
+template <class C>
+__device__ __forceinline__ void christoffels(const C (&gu)[6], const C (&dg)[3][6], C (&Gl)[3][6],
+                                             C (&Gu)[3][6], C (&Gd)[3])
 {
-    // With CONS, rhs[0..7] receives the constraint monitors instead:
-    // H, M^x, M^y, M^z, Theta, G^x, G^y, G^z.
-    const int st[3] = {1, sy, sz};
-#pragma unroll
-    for (int f = 0; f < NF; ++f) v[f] = (C)z[f * slab];
-
-    const C chi = v[F_CHI], Kh = v[F_KH], Th = v[F_TH], al = v[F_ALPHA];
-    C g[6], A[6], Gam[3], be[3];
-#pragma unroll
-    for (int p = 0; p < 6; ++p) { g[p] = v[F_GXX + p]; A[p] = v[F_AXX + p]; }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) { Gam[i] = v[F_GAMX + i]; be[i] = v[F_BETAX + i]; }
-
-    // ---- first derivatives (d[a] = d_a)
-    C dg[3][6], dchi[3], dal[3], dKh[3], dTh[3], dbe[3][3], dGam[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int s = st[a];
-#pragma unroll
-        for (int p = 0; p < 6; ++p) dg[a][p] = ih * fd1<N, C>(z + (F_GXX + p) * slab, s);
-        dchi[a] = ih * fd1<N, C>(z + F_CHI * slab, s);
-        dal[a] = ih * fd1<N, C>(z + F_ALPHA * slab, s);
-        dKh[a] = ih * fd1<N, C>(z + F_KH * slab, s);
-        dTh[a] = ih * fd1<N, C>(z + F_TH * slab, s);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            dbe[a][i] = ih * fd1<N, C>(z + (F_BETAX + i) * slab, s);
-            dGam[a][i] = ih * fd1<N, C>(z + (F_GAMX + i) * slab, s);
-        }
-    }
-
-    // ---- inverse conformal metric
-    C gu[6];
-    {
-        const C c0 = g[3] * g[5] - g[4] * g[4];
-        const C c1 = g[2] * g[4] - g[1] * g[5];
-        const C c2 = g[1] * g[4] - g[2] * g[3];
-        const C det = g[0] * c0 + g[1] * c1 + g[2] * c2;
-        const C id = (C)1 / det;
-        gu[0] = c0 * id;
-        gu[1] = c1 * id;
-        gu[2] = c2 * id;
-        gu[3] = (g[0] * g[5] - g[2] * g[2]) * id;
-        gu[4] = (g[1] * g[2] - g[0] * g[4]) * id;
-        gu[5] = (g[0] * g[3] - g[1] * g[1]) * id;
-    }
-    const C ic = inv_chi<C>(chi, P.chi_floor);
-    const C K = Kh + (C)2 * Th;
-
-    // ---- Christoffel symbols: Gl[k][ij] = G~_kij, Gu[k][ij] = G~^k_ij
-    C Gl[3][6], Gu[3][6], Gd[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -177,9 +109,78 @@ __device__ __forceinline__ void zone_rhs(const T* __restrict__ z, int64_t slab, 
         for (int p = 0; p < 6; ++p) s += (C)SW(p) * gu[p] * Gu[i][p];
         Gd[i] = s;
     }
+}
 
-    // ---- A~^ij, A~_ij A~^ij, A~_ik g~^kl (mixed)
-    C Am[3][3];  // Am[i][l] = A~_ik g~^kl
+// Full Ricci tensor R_ij = R~_ij + R^chi_ij and scalar R = chi g~^ij R_ij.
+// Rt holds on entry -1/2 g~^lm d_l d_m g~_ij + 1/2 (g~_ki d_j G~^k + g~_kj d_i G~^k).
+template <class C>
+__device__ __forceinline__ void ricci(const C (&gdn)[6], const C (&gu)[6], const C (&Gl)[3][6],
+                                      const C (&Gu)[3][6], const C (&Gd)[3], C chi, C ic,
+                                      const C (&dchi)[3], const C (&ddchi)[6], C (&Rt)[6],
+                                      C (&Rij)[6], C& Rs)
+{
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        const int i = SA(p), j = SB(p);
+        C s = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s += Gd[k] * (C)0.5 * (Gl[i][S(j, k)] + Gl[j][S(i, k)]);
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                C t = 0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    t += Gu[k][S(l, i)] * Gl[j][S(k, m)] + Gu[k][S(l, j)] * Gl[i][S(k, m)] +
+                         Gu[k][S(i, m)] * Gl[k][S(l, j)];
+                s += gu[S(l, m)] * t;
+            }
+        Rt[p] += s;
+    }
+    C Dchi[6], trD = 0, dc2 = 0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p)
+        Dchi[p] = ddchi[p] - (Gu[0][p] * dchi[0] + Gu[1][p] * dchi[1] + Gu[2][p] * dchi[2]);
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        trD += (C)SW(p) * gu[p] * Dchi[p];
+        dc2 += (C)SW(p) * gu[p] * dchi[SA(p)] * dchi[SB(p)];
+    }
+    Rs = 0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        const int i = SA(p), j = SB(p);
+        Rij[p] = Rt[p] + (C)0.5 * ic * Dchi[p] + (C)0.5 * ic * gdn[p] * trD -
+                 (C)0.25 * ic * ic * dchi[i] * dchi[j] - (C)0.75 * ic * ic * gdn[p] * dc2;
+        Rs += (C)SW(p) * gu[p] * Rij[p];
+    }
+    Rs *= chi;
+}
+
+// The algebraic part of the 22 right-hand sides (everything except the
+// advection and dissipation terms) from centre values and derivatives:
+//   dg[a][p] = d_a g~_p, dbe[a][i] = d_a beta^i, Lb[i] = g~^jk d_j d_k beta^i,
+//   Bj[j] = d_j d_k beta^k, eK[j] = d_j (2 Khat + Theta), Rt as for ricci().
+template <class C>
+__device__ __forceinline__ void z4c_algebra(const ParamsDev& P, C chi, const C (&gdn)[6],
+                                            const C (&gu)[6], C Kh, const C (&A)[6],
+                                            const C (&Gam)[3], C Th, C al, const C (&be)[3],
+                                            const C (&dg)[3][6], const C (&dchi)[3],
+                                            const C (&ddchi)[6], const C (&dal)[3],
+                                            const C (&ddal)[6], const C (&dbe)[3][3],
+                                            const C (&Lb)[3], const C (&Bj)[3], const C (&eK)[3],
+                                            C (&Rt)[6], C (&rhs)[NF])
+{
+    C Gl[3][6], Gu[3][6], Gd[3];
+    christoffels<C>(gu, dg, Gl, Gu, Gd);
+    const C ic = inv_chi<C>(chi, P.chi_floor);
+    const C K = Kh + (C)2 * Th;
+    C Rij[6], Rs;
+    ricci<C>(gdn, gu, Gl, Gu, Gd, chi, ic, dchi, ddchi, Rt, Rij, Rs);
+
+    // A~_ik g~^kl, A~^ij, A~_ij A~^ij
+    C Am[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -195,165 +196,31 @@ __device__ __forceinline__ void zone_rhs(const T* __restrict__ z, int64_t slab, 
 #pragma unroll
     for (int p = 0; p < 6; ++p) AA += (C)SW(p) * A[p] * Au[p];
 
-    // ---- second derivatives, contracted as they are produced
-    // Rt[ij] starts with -1/2 g~^lm d_l d_m g~_ij
-    C Rt[6], ddchi[6], ddal[6], Lb[3], Bj[3];
+    // D_i D_j alpha and its trace D^i D_i alpha
+    C DDa[6], trDDa = 0, cda = 0;
 #pragma unroll
-    for (int p = 0; p < 6; ++p) Rt[p] = 0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) { Lb[i] = 0; Bj[i] = 0; }
-    const C ih2 = ih * ih;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const int a = SA(q), b = SB(q);
-        const C wq = (C)(-0.5 * SW(q)) * gu[q] * ih2;
-#pragma unroll
-        for (int p = 0; p < 6; ++p) {
-            const T* pf = z + (F_GXX + p) * slab;
-            const C d = (a == b) ? fd2<N, C>(pf, st[a]) : fdmix<N, C>(pf, st[a], st[b]);
-            Rt[p] += wq * d;
-        }
-        {
-            const T* pf = z + F_CHI * slab;
-            ddchi[q] = ih2 * ((a == b) ? fd2<N, C>(pf, st[a]) : fdmix<N, C>(pf, st[a], st[b]));
-            pf = z + F_ALPHA * slab;
-            ddal[q] = ih2 * ((a == b) ? fd2<N, C>(pf, st[a]) : fdmix<N, C>(pf, st[a], st[b]));
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const T* pf = z + (F_BETAX + i) * slab;
-            const C d = ih2 * ((a == b) ? fd2<N, C>(pf, st[a]) : fdmix<N, C>(pf, st[a], st[b]));
-            Lb[i] += (C)SW(q) * gu[q] * d;          // g~^jk d_j d_k beta^i
-            // B_j = d_j d_k beta^k: pair q=(a,b) contributes to B_a if i==b, B_b if i==a
-            if (i == b) Bj[a] += d;
-            if (a != b && i == a) Bj[b] += d;
-        }
-    }
-
-    // ---- rest of the conformal Ricci tensor
+    for (int p = 0; p < 6; ++p)
+        cda += (C)SW(p) * gu[p] * (C)0.5 * (dchi[SA(p)] * dal[SB(p)] + dchi[SB(p)] * dal[SA(p)]);
 #pragma unroll
     for (int p = 0; p < 6; ++p) {
         const int i = SA(p), j = SB(p);
-        C s = 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            s += (C)0.5 * (g[S(k, i)] * dGam[j][k] + g[S(k, j)] * dGam[i][k]) +
-                 Gd[k] * (C)0.5 * (Gl[i][S(j, k)] + Gl[j][S(i, k)]);
-#pragma unroll
-        for (int l = 0; l < 3; ++l)
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                C t = 0;
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-                    t += Gu[k][S(l, i)] * Gl[j][S(k, m)] + Gu[k][S(l, j)] * Gl[i][S(k, m)] +
-                         Gu[k][S(i, m)] * Gl[k][S(l, j)];
-                s += gu[S(l, m)] * t;
-            }
-        Rt[p] += s;
+        DDa[p] = ddal[p] - (Gu[0][p] * dal[0] + Gu[1][p] * dal[1] + Gu[2][p] * dal[2]) +
+                 (C)0.5 * ic * (dchi[i] * dal[j] + dchi[j] * dal[i] - gdn[p] * cda);
+        trDDa += (C)SW(p) * gu[p] * DDa[p];
     }
-
-    // ---- conformal-factor part and the full Ricci tensor
-    C Rij[6];
-    {
-        C Dchi[6], trD = 0, dc2 = 0;
-#pragma unroll
-        for (int p = 0; p < 6; ++p)
-            Dchi[p] = ddchi[p] - (Gu[0][p] * dchi[0] + Gu[1][p] * dchi[1] + Gu[2][p] * dchi[2]);
-#pragma unroll
-        for (int p = 0; p < 6; ++p) {
-            trD += (C)SW(p) * gu[p] * Dchi[p];
-            dc2 += (C)SW(p) * gu[p] * dchi[SA(p)] * dchi[SB(p)];
-        }
-#pragma unroll
-        for (int p = 0; p < 6; ++p) {
-            const int i = SA(p), j = SB(p);
-            Rij[p] = Rt[p] + (C)0.5 * ic * Dchi[p] + (C)0.5 * ic * g[p] * trD -
-                     (C)0.25 * ic * ic * dchi[i] * dchi[j] - (C)0.75 * ic * ic * g[p] * dc2;
-        }
-    }
-    C Rs = 0;
-#pragma unroll
-    for (int p = 0; p < 6; ++p) Rs += (C)SW(p) * gu[p] * Rij[p];
-    Rs *= chi;
-
-    // ---- D_i D_j alpha
-    C DDa[6], trDDa = 0;
-    {
-        C cda = 0;
-#pragma unroll
-        for (int p = 0; p < 6; ++p) {
-            const int i = SA(p), j = SB(p);
-            cda += (C)SW(p) * gu[p] * (C)0.5 * (dchi[i] * dal[j] + dchi[j] * dal[i]);
-        }
-#pragma unroll
-        for (int p = 0; p < 6; ++p) {
-            const int i = SA(p), j = SB(p);
-            DDa[p] = ddal[p] - (Gu[0][p] * dal[0] + Gu[1][p] * dal[1] + Gu[2][p] * dal[2]) +
-                     (C)0.5 * ic * (dchi[i] * dal[j] + dchi[j] * dal[i] - g[p] * cda);
-            trDDa += (C)SW(p) * gu[p] * DDa[p];
-        }
-        trDDa *= chi;
-    }
-
-    if constexpr (CONS) {
-        // H = R - A~_ij A~^ij + (2/3) K^2
-        rhs[0] = Rs - AA + (C)(2.0 / 3.0) * K * K;
-        // M^i = d_j A~^ij + G~^i_jk A~^jk - (2/3) g~^ij d_j K - (3/2) A~^ij d_j chi / chi
-        C dA[3][6], dgu[3][6];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int p = 0; p < 6; ++p) dA[a][p] = ih * fd1<N, C>(z + (F_AXX + p) * slab, st[a]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int p = 0; p < 6; ++p) {
-                const int i = SA(p), j = SB(p);
-                C s = 0;
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) s -= gu[S(i, c)] * gu[S(j, d)] * dg[a][S(c, d)];
-                dgu[a][p] = s;
-            }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            C s = 0;
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int l = 0; l < 3; ++l)
-                        s += dgu[j][S(i, k)] * gu[S(j, l)] * A[S(k, l)] +
-                             gu[S(i, k)] * dgu[j][S(j, l)] * A[S(k, l)] +
-                             gu[S(i, k)] * gu[S(j, l)] * dA[j][S(k, l)];
-#pragma unroll
-            for (int p = 0; p < 6; ++p) s += (C)SW(p) * Gu[i][p] * Au[p];
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                s -= (C)(2.0 / 3.0) * gu[S(i, j)] * (dKh[j] + (C)2 * dTh[j]) +
-                     (C)1.5 * Au[S(i, j)] * dchi[j] * ic;
-            rhs[1 + i] = s;
-            rhs[5 + i] = Gam[i] - Gd[i];
-        }
-        rhs[4] = Th;
-        return;
-    }
+    trDDa *= chi;
 
     const C divb = dbe[0][0] + dbe[1][1] + dbe[2][2];
 #pragma unroll
     for (int f = 0; f < NF; ++f) rhs[f] = 0;
-
     if (P.terms & 1u) {
         rhs[F_CHI] = (C)(2.0 / 3.0) * chi * (al * K - divb);
 #pragma unroll
         for (int p = 0; p < 6; ++p) {
             const int i = SA(p), j = SB(p);
-            C s = (C)-2 * al * A[p] - (C)(2.0 / 3.0) * g[p] * divb;
+            C s = (C)-2 * al * A[p] - (C)(2.0 / 3.0) * gdn[p] * divb;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) s += g[S(i, k)] * dbe[j][k] + g[S(j, k)] * dbe[i][k];
+            for (int k = 0; k < 3; ++k) s += gdn[S(i, k)] * dbe[j][k] + gdn[S(j, k)] * dbe[i][k];
             rhs[F_GXX + p] = s;
         }
         rhs[F_KH] = -trDDa + al * (AA + K * K / (C)3) + (C)(P.kappa1 * (1.0 - P.kappa2)) * al * Th;
@@ -366,7 +233,7 @@ __device__ __forceinline__ void zone_rhs(const T* __restrict__ z, int64_t slab, 
 #pragma unroll
         for (int p = 0; p < 6; ++p) {
             const int i = SA(p), j = SB(p);
-            C s = chi * (X[p] - g[p] * trX / (C)3);
+            C s = chi * (X[p] - gdn[p] * trX / (C)3);
             const C AgA = Am[i][0] * A[S(0, j)] + Am[i][1] * A[S(1, j)] + Am[i][2] * A[S(2, j)];
             s += al * (K * A[p] - (C)2 * AgA);
 #pragma unroll
@@ -383,8 +250,7 @@ __device__ __forceinline__ void zone_rhs(const T* __restrict__ z, int64_t slab, 
 #pragma unroll
             for (int p = 0; p < 6; ++p) t += (C)SW(p) * Gu[i][p] * Au[p];
             t -= (C)1.5 * ic * (Au[S(i, 0)] * dchi[0] + Au[S(i, 1)] * dchi[1] + Au[S(i, 2)] * dchi[2]);
-            t -= (gu[S(i, 0)] * ((C)2 * dKh[0] + dTh[0]) + gu[S(i, 1)] * ((C)2 * dKh[1] + dTh[1]) +
-                  gu[S(i, 2)] * ((C)2 * dKh[2] + dTh[2])) / (C)3;
+            t -= (gu[S(i, 0)] * eK[0] + gu[S(i, 1)] * eK[1] + gu[S(i, 2)] * eK[2]) / (C)3;
             s += (C)2 * al * t;
             s -= (C)2 * al * (C)P.kappa1 * (Gam[i] - Gd[i]);
             rhs[F_GAMX + i] = s;
@@ -397,31 +263,129 @@ __device__ __forceinline__ void zone_rhs(const T* __restrict__ z, int64_t slab, 
 #pragma unroll
         for (int i = 0; i < 3; ++i) rhs[F_BETAX + i] = (C)P.mu_S * Gam[i] - (C)P.eta * be[i];
     }
+}
 
-    // ---- advection (lopsided, upwinded by the sign of beta) + Kreiss-Oliger
-    const bool adv = (P.terms & 4u) != 0;
-    const bool adv_gauge = adv && (P.terms & 2u);
-    const C sig = (P.terms & 8u) ? (C)P.ko_sigma : (C)0;
-    C ev[3][N + 2], evk[N + 2];  // even coefficients with / without advection
+// Constraint monitors of one zone (direct stencil reads, double):
+// out = H, M^x, M^y, M^z, Theta, G^x, G^y, G^z with
+//   H = R - A~_ij A~^ij + (2/3) K^2,
+//   M^i = d_j A~^ij + G~^i_jk A~^jk - (2/3) g~^ij d_j K - (3/2) A~^ij d_j chi / chi,
+//   G^i = G~^i - G~d^i.
+template <int N, class T>
+__device__ __forceinline__ void zone_constraints(const T* __restrict__ z, int64_t slab, int sy,
+                                                 int sz, double ih, const ParamsDev& P,
+                                                 double (&out)[8])
+{
+    using C = double;
+    const int st[3] = {1, sy, sz};
+    auto cen = [&](int f) { return (C)z[f * slab]; };
+    const C chi = cen(F_CHI), Kh = cen(F_KH), Th = cen(F_TH);
+    C gdn[6], A[6], Gam[3];
 #pragma unroll
-    for (int k = 1; k <= N + 1; ++k) {
-        evk[k] = sig * (C)Stencil<N>::KO[k];
+    for (int p = 0; p < 6; ++p) { gdn[p] = cen(F_GXX + p); A[p] = cen(F_AXX + p); }
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-            ev[a][k] = (adv ? (C)fabs((double)be[a]) * (C)lop_even<N>(k) : (C)0) + evk[k];
+    for (int i = 0; i < 3; ++i) Gam[i] = cen(F_GAMX + i);
+    C gu[6];
+    {
+        const C c0 = gdn[3] * gdn[5] - gdn[4] * gdn[4];
+        const C c1 = gdn[2] * gdn[4] - gdn[1] * gdn[5];
+        const C c2 = gdn[1] * gdn[4] - gdn[2] * gdn[3];
+        const C id = 1.0 / (gdn[0] * c0 + gdn[1] * c1 + gdn[2] * c2);
+        gu[0] = c0 * id; gu[1] = c1 * id; gu[2] = c2 * id;
+        gu[3] = (gdn[0] * gdn[5] - gdn[2] * gdn[2]) * id;
+        gu[4] = (gdn[1] * gdn[2] - gdn[0] * gdn[4]) * id;
+        gu[5] = (gdn[0] * gdn[3] - gdn[1] * gdn[1]) * id;
+    }
+    C dg[3][6], dchi[3], ddchi[6], dK[3], dA[3][6], Rt[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            dg[a][p] = ih * fd1<N, C>(z + (F_GXX + p) * slab, st[a]);
+            dA[a][p] = ih * fd1<N, C>(z + (F_AXX + p) * slab, st[a]);
+        }
+        dchi[a] = ih * fd1<N, C>(z + F_CHI * slab, st[a]);
+        dK[a] = ih * (fd1<N, C>(z + F_KH * slab, st[a]) + 2.0 * fd1<N, C>(z + F_TH * slab, st[a]));
+    }
+    const C ih2 = ih * ih;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) Rt[p] = 0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const int a = SA(q), b = SB(q);
+        const C wq = -0.5 * SW(q) * gu[q] * ih2;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const T* pf = z + (F_GXX + p) * slab;
+            Rt[p] += wq * ((a == b) ? fd2<N, C>(pf, st[a]) : fdmix<N, C>(pf, st[a], st[b]));
+        }
+        const T* pf = z + F_CHI * slab;
+        ddchi[q] = ih2 * ((a == b) ? fd2<N, C>(pf, st[a]) : fdmix<N, C>(pf, st[a], st[b]));
     }
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-        const bool gauge_field = (f == F_ALPHA || f >= F_BETAX);
-        const bool a_on = gauge_field ? adv_gauge : adv;
-        C s = 0;
+    for (int k = 0; k < 3; ++k)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const C va = a_on ? be[a] : (C)0;
-            s += fadvdiss<N, C>(z + f * slab, st[a], va, a_on ? ev[a] : evk);
+            const C dG = ih * fd1<N, C>(z + (F_GAMX + k) * slab, st[a]);
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                const int i = SA(p), j = SB(p);
+                if (a == j) Rt[p] += 0.5 * gdn[S(k, i)] * dG;
+                if (a == i) Rt[p] += 0.5 * gdn[S(k, j)] * dG;
+            }
         }
-        rhs[f] += ih * s;
+    C Gl[3][6], Gu[3][6], Gd[3];
+    christoffels<C>(gu, dg, Gl, Gu, Gd);
+    const C ic = inv_chi<C>(chi, P.chi_floor);
+    C Rij[6], Rs;
+    ricci<C>(gdn, gu, Gl, Gu, Gd, chi, ic, dchi, ddchi, Rt, Rij, Rs);
+    C Au[6], AA = 0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        const int i = SA(p), j = SB(p);
+        C s = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int l = 0; l < 3; ++l) s += gu[S(i, k)] * gu[S(j, l)] * A[S(k, l)];
+        Au[p] = s;
     }
+#pragma unroll
+    for (int p = 0; p < 6; ++p) AA += SW(p) * A[p] * Au[p];
+    const C K = Kh + 2.0 * Th;
+    out[0] = Rs - AA + (2.0 / 3.0) * K * K;
+    C dgu[3][6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const int i = SA(p), j = SB(p);
+            C s = 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) s -= gu[S(i, c)] * gu[S(j, d)] * dg[a][S(c, d)];
+            dgu[a][p] = s;
+        }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        C s = 0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int l = 0; l < 3; ++l)
+                    s += dgu[j][S(i, k)] * gu[S(j, l)] * A[S(k, l)] +
+                         gu[S(i, k)] * dgu[j][S(j, l)] * A[S(k, l)] +
+                         gu[S(i, k)] * gu[S(j, l)] * dA[j][S(k, l)];
+#pragma unroll
+        for (int p = 0; p < 6; ++p) s += SW(p) * Gu[i][p] * Au[p];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) s -= (2.0 / 3.0) * gu[S(i, j)] * dK[j] + 1.5 * Au[S(i, j)] * dchi[j] * ic;
+        out[1 + i] = s;
+        out[5 + i] = Gam[i] - Gd[i];
+    }
+    out[4] = Th;
 }
 
 // Algebraic constraints and floors on one zone's state, in double.

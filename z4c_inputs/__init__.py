@@ -126,6 +126,32 @@ def split_blocks(mesh: Mesh, which) -> Mesh:
                 bc=mesh.bc, lo=mesh.lo, dx0=mesh.dx0)
 
 
+def nested_bbh_mesh(g: int = 5) -> Mesh:
+    """512 MeshBlocks over four levels around two punctures at x = +-5:
+    root 4^3 blocks of 32^3 (dx = 1) on [-64, 64]^3; level 1 (dx = 1/2) on
+    [-32, 32]^3, level 2 (dx = 1/4) on [-16, 16]^3, both in 32^3 blocks;
+    level 3 (dx = 1/8) on [-8, 8]^3 in 4-unit blocks of which five of the
+    eight (inner/outer per axis) classes are split into 16^3 blocks:
+    56 + 56 + 56 + 24 x 32^3 + 320 x 16^3 = 512 blocks, 7,602,176 zones."""
+    m = uniform_mesh((4, 4, 4), 32, g, (-64.0,) * 3, (64.0,) * 3, BC_OUTFLOW)
+    m = refine_blocks(m, blocks_in_box(m, (-32.0,) * 3, (32.0,) * 3))
+    m = refine_blocks(m, blocks_in_box(m, (-16.0,) * 3, (16.0,) * 3))
+    m = refine_blocks(m, blocks_in_box(m, (-8.0,) * 3, (8.0,) * 3))
+    split_classes = {("o", "i", "i"), ("o", "o", "i"), ("o", "i", "o"), ("i", "i", "i"), ("o", "o", "o")}
+    which = []
+    for b in range(m.nb):
+        if m.level[b] != 3:
+            continue
+        h = m.dx(b)
+        cls = []
+        for a in range(3):
+            x0 = m.lo[a] + m.ilo[b, a] * h          # block spans [x0, x0 + 4]
+            cls.append("i" if -4.0 <= x0 < 4.0 else "o")
+        if tuple(cls) in split_classes:
+            which.append(b)
+    return split_blocks(m, which)
+
+
 def blocks_in_box(mesh: Mesh, lo, hi):
     """Indices of blocks whose interior lies inside the physical box [lo, hi]."""
     out = []
@@ -231,6 +257,8 @@ def workload(name: str):
                 Brill-Lindquist M = 1 at the origin, outflow, dt = 0.0625.
     bl512x32    512 blocks of 32^3 on [-16,16]^3 (dx = 0.125), 6th order,
                 BL M = 1 plus 8 sinusoids of 1e-6 per field (seed 4).
+    bbh512mixed 512 blocks of 16^3 and 32^3 over 4 levels (nested_bbh_mesh),
+                8th order, 5 ghosts, two BL punctures m = 0.5 at x = +-5.
     bbh4096x16  4096 blocks of 16^3 on [-16,16]^3 (dx = 0.125), 6th order,
                 two BL punctures m = 0.5 at x = +-5.
     """
@@ -247,6 +275,10 @@ def workload(name: str):
         mesh = uniform_mesh((8, 8, 8), 32, 4, (-16.0,) * 3, (16.0,) * 3, BC_OUTFLOW)
         data = add_perturbation(mesh, brill_lindquist(mesh, [(1.0, (0.0, 0.0, 0.0))]), seed=4)
         return mesh, params_default(6, eta=2.0), data, cfl * mesh.dx0, 100
+    if name == "bbh512mixed":
+        mesh = nested_bbh_mesh()
+        data = brill_lindquist(mesh, [(0.5, (5.0, 0.0, 0.0)), (0.5, (-5.0, 0.0, 0.0))])
+        return mesh, params_default(8, eta=2.0), data, cfl * mesh.dx(int(np.argmax(mesh.level))), 1
     if name == "bbh4096x16":
         mesh = uniform_mesh((16, 16, 16), 16, 4, (-16.0,) * 3, (16.0,) * 3, BC_OUTFLOW)
         data = brill_lindquist(mesh, [(0.5, (5.0, 0.0, 0.0)), (0.5, (-5.0, 0.0, 0.0))])
