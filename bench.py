@@ -97,7 +97,7 @@ def main():
     pack.profile(True)
     pack.profile_read(reset=True)
     pack.rk4_step(dt, args.profile_steps)
-    st_ms, st_n, fill_ms, fill_n = pack.profile_read(reset=True)
+    st_ms, st_n, fill_ms, fill_n, _, _ = pack.profile_read(reset=True)
     pack.profile(False)
     avg_stage_s = st_ms / st_n * 1e-3
     bpl = BYTES_PER_ZONE_LAUNCH[args.precision] * pack.zones

@@ -81,7 +81,8 @@ enum {
 };
 enum {
     Z4C_FLAG_ENFORCE = 1,       /* det g~ = 1, tr A~ = 0, floors after writes */
-    Z4C_FLAG_CHECK_FINITE = 2   /* z4c_rk4_step checks U for NaN/Inf         */
+    Z4C_FLAG_CHECK_FINITE = 2,  /* reserved                                 */
+    Z4C_FLAG_GRAPH = 4          /* z4c_rk4_step replays a captured hipGraph  */
 };
 
 /* One MeshBlock: cubic, n^3 active cells at refinement `level`, lower
@@ -202,8 +203,27 @@ int z4c_rhs(struct z4c_pack *pack, int32_t src_reg, void *rhs_out, void *stream)
  * chi/alpha floors on the written state.  A accumulates in double. */
 int z4c_rk4_stage(struct z4c_pack *pack, int32_t stage, double dt, void *stream);
 
-/* nsteps full RK4 steps of U (four stages each). */
+/* nsteps full RK4 steps of U (four stages each).  With Z4C_FLAG_GRAPH and a
+ * non-NULL stream, the four stages (ghost fills included) are captured once
+ * into a hipGraph per (dt, stream) and replayed for every step. */
 int z4c_rk4_step(struct z4c_pack *pack, double dt, int32_t nsteps, void *stream);
+
+/* Launch configuration of the fused stage kernel (batching, Sec. 3:
+ * MeshBlockPacks exist to cut kernel launches): tile-shape variant
+ * (0: 8x8x4, 1: 16x4x4, 2: 8x4x8, 3: 16x8x2 active cells per workgroup)
+ * and persistent mode (one grid sized to the resident workgroups, each
+ * looping over its XCD's contiguous share of the tiles).  Every variant
+ * computes bitwise-identical results.  Z4C_EUNSUPPORTED if the shape does
+ * not divide every block.  Synchronises the stream. */
+int z4c_set_variant(struct z4c_pack *pack, int32_t variant, int32_t persistent, void *stream);
+
+/* Autotuner: times `reps` RHS launches of every (variant, persistent)
+ * pair that fits the pack, times_ms[2*variant + persistent] (host, 8
+ * doubles, -1 where not applicable, nullable), selects the fastest and
+ * returns its index in *chosen.  Uses the accumulator register as scratch
+ * (call between RK4 steps).  Synchronises the stream. */
+int z4c_autotune(struct z4c_pack *pack, int32_t reps, double *times_ms, int32_t *chosen,
+                 void *stream);
 
 /* Constraint monitors in double: Hamiltonian H, momentum M^i, Theta and
  * G^i = Gamma~^i - Gamma~_d^i at every active zone of state register `reg`
@@ -221,12 +241,92 @@ int z4c_constraints(struct z4c_pack *pack, int32_t reg, void *per_zone_out,
 int z4c_refine_flags(struct z4c_pack *pack, int32_t reg, const z4c_refine_params *rp,
                      int8_t *flags_out, void *stream);
 
+/* ----------------------------------------------- learned refinement */
+/* The learned indicator predicts, per MeshBlock, the truncation error the
+ * chi-based criteria of Sec. 3.3 stand in for, from cheap block features;
+ * the plain dchi-max criterion stays as fallback and judge.  Features (16
+ * per block, double): 0 max|d chi| 1 mean|d chi| 2 max|d alpha|
+ * 3 mean|d alpha| 4 max|dd g~| 5 mean|dd g~| 6 min alpha 7 min chi
+ * 8 max|Khat| 9 max|A~| 10 max|Theta| 11 max|Gamma~| 12 max|beta|
+ * 13 max|dd chi| 14 max|d Khat| 15 log2 dx, reduced over active zones
+ * (centred derivatives of the pack's order; vector and tensor norms
+ * Euclidean, |dd f| the largest component). */
+#define Z4C_MLP_NPARAM 5313   /* W1[64][16] b1[64] W2[64][64] b2[64] W3[64] b3[1] */
+
+/* Features of state register `reg` (ghosts filled first unless USER) into
+ * feat_dev (device double[nblocks*16], nullable) and/or feat_host (host,
+ * nullable; synchronises the stream). */
+int z4c_features(struct z4c_pack *pack, int32_t reg, void *feat_dev, double *feat_host,
+                 void *stream);
+
+/* Injection onto the even sublattice: active cell J of block b of pack_2h's
+ * register reg_2h gets active cell 2J of block b of pack_h's register
+ * reg_h.  pack_2h must have the same number of blocks, each with n/2 cells
+ * and corner ilo/2 at the same level (its cell size 2h, its domain shifted
+ * by -h/2 so that its centres are the even fine centres). */
+int z4c_pack_inject_2h(struct z4c_pack *pack_h, int32_t reg_h, struct z4c_pack *pack_2h,
+                       int32_t reg_2h, void *stream);
+
+/* Truncation-error labels: y_b = log10(sqrt(mean over the active cells J of
+ * block b of pack_2h and the 22 fields of (rhs_h(2J) - rhs_2h(J))^2) + 1e-30)
+ * from two z4c_rhs outputs (device, interior layout).  labels_out: host
+ * double[nblocks].  Synchronises the stream. */
+int z4c_labels(struct z4c_pack *pack_h, const void *rhs_h, struct z4c_pack *pack_2h,
+               const void *rhs_2h, double *labels_out, void *stream);
+
+/* phi(raw) statistics over a batch of B feature rows (device double
+ * raw[B*16]; phi = log10(|x| + 1e-12) for features 0..14, identity for 15):
+ * stats (device double[64]) = mean[16], std[16], min[16], max[16]. */
+int z4c_feature_stats(const void *raw, int32_t B, void *stats, void *stream);
+/* Network inputs X[b][k] = (phi(raw[b][k]) - mean[k]) / std[k] (device float). */
+int z4c_mlp_normalize(const void *raw, int32_t B, const void *stats, void *X, void *stream);
+
+/* 16 -> 64 -> 64 -> 1 perceptron, ReLU hidden layers, linear output.
+ * Inputs, weights and hidden activations are rounded to bfloat16 (nearest
+ * even); sums accumulate in float32.  params: device float[Z4C_MLP_NPARAM]
+ * (float32 master weights).  X: device float[B*16]; Y: device float[B];
+ * cache (nullable for inference): device float[B*128] pre-activations. */
+int z4c_mlp_forward(const void *params, const void *X, int32_t B, void *Y, void *cache,
+                    void *stream);
+/* Gradient of the mean squared error (Y from z4c_mlp_forward with cache,
+ * targets T device float[B]) with respect to the master weights (through
+ * the rounding as identity): grad device float[Z4C_MLP_NPARAM]; loss device
+ * float[1] (nullable); work device float[B*129]. */
+int z4c_mlp_backward(const void *params, const void *X, const void *Y, const void *T,
+                     const void *cache, int32_t B, void *grad, void *loss, void *work,
+                     void *stream);
+/* One Adam step (step counts from 1) on params with moments m, v (device
+ * float[Z4C_MLP_NPARAM] each). */
+int z4c_mlp_adam(void *params, const void *grad, void *m, void *v, int32_t step, float lr,
+                 float beta1, float beta2, float eps, void *stream);
+
+typedef struct {
+    const void *params;    /* device float[Z4C_MLP_NPARAM]                    */
+    const void *stats;     /* device double[64] from z4c_feature_stats        */
+    const double *range;   /* host double[32]: phi min[16], max[16] of training */
+    double tau_ref;        /* predicted log10 error above which to refine     */
+    double tau_deref;      /* ... below which to derefine                     */
+    double chi_thr;        /* chi-min safety: min chi < chi_thr forces +1     */
+    double dchi_thr;       /* dchi-max threshold of the fallback              */
+    int32_t level_max;
+    int32_t pad;
+} z4c_mlp_model;
+
+/* Learned refinement flags: features -> network -> +1 if prediction >
+ * tau_ref, -1 if < tau_deref, else 0; min chi < chi_thr forces +1; a block
+ * whose features are non-finite or outside the training range widened by
+ * 10% takes the dchi-max flag instead (fallback_out[b] = 1, nullable).
+ * Level limits as z4c_refine_flags.  Synchronises the stream. */
+int z4c_refine_flags_learned(struct z4c_pack *pack, int32_t reg, const z4c_mlp_model *model,
+                             int8_t *flags_out, int8_t *fallback_out, void *stream);
+
 /* Kernel timing for benchmarks.  With enable = 1, every later stage-kernel
  * and ghost-fill launch on this pack is bracketed by a pair of HIP events
  * recorded on the launch stream; z4c_profile_read waits for them and
  * returns out[0] total stage-kernel milliseconds, out[1] stage launches,
- * out[2] ghost-fill milliseconds, out[3] fill launches (reset != 0 clears
- * the totals).  Events are host-side HIP objects; no device memory. */
+ * out[2] ghost-fill milliseconds, out[3] fill launches, out[4] captured-step
+ * (hipGraph) milliseconds, out[5] graph launches (reset != 0 clears the
+ * totals).  Events are host-side HIP objects; no device memory. */
 int z4c_profile(struct z4c_pack *pack, int32_t enable);
 int z4c_profile_read(struct z4c_pack *pack, double *out, int32_t reset);
 

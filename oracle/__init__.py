@@ -217,6 +217,17 @@ def constraints(om: OracleMesh, params: dict, u: np.ndarray, exclude=(), r_exc: 
 CRIT_CHI_MIN, CRIT_DCHI_MAX, CRIT_RADIUS = 0, 1, 2
 
 
+def block_features(om: OracleMesh, params: dict, u: np.ndarray, fill: bool = True) -> np.ndarray:
+    """(nb, 16) raw per-block features (see features.c)."""
+    if fill:
+        fill_ghosts(om, u)
+    out = np.zeros((om.mesh.nb, 16))
+    rc = lib().or_block_features(C.byref(om.c), C.byref(make_params(params)), _dp(u), _dp(out))
+    if rc:
+        raise RuntimeError(f"oracle features failed ({rc})")
+    return out
+
+
 def refine_flags(om: OracleMesh, params: dict, u: np.ndarray, criterion: int, chi_thr=0.3,
                  dchi_thr=0.1, level_max=10, radius=0.0, centre=(0.0, 0.0, 0.0),
                  radius_level=0, fill: bool = True) -> np.ndarray:

@@ -90,4 +90,7 @@ int or_refine_flags(const or_mesh *m, const or_params *p, const double *u,
                     int level_max, double radius, const double *centre,
                     int radius_level, int8_t *flags);
 
+/* 16 raw per-block features for the learned refinement indicator */
+int or_block_features(const or_mesh *m, const or_params *p, const double *u, double *feat);
+
 #endif

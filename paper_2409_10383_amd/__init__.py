@@ -21,7 +21,7 @@ REG_U, REG_S1, REG_S2, REG_A = 0, 1, 2, 3
 BC_PERIODIC, BC_OUTFLOW, BC_USER = 0, 1, 2
 FP64, FP32_MIXED = 0, 1
 TERM_PHYS, TERM_GAUGE, TERM_ADVECT, TERM_DISSIP, TERM_ALL = 1, 2, 4, 8, 15
-FLAG_ENFORCE, FLAG_CHECK_FINITE = 1, 2
+FLAG_ENFORCE, FLAG_CHECK_FINITE, FLAG_GRAPH = 1, 2, 4
 CRIT_CHI_MIN, CRIT_DCHI_MAX, CRIT_RADIUS = 0, 1, 2
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "ENONFINITE",
           -6: "EUNSUPPORTED"}
@@ -66,7 +66,16 @@ class RefineParams(C.Structure):
 EXPORTS = ["z4c_pack_create", "z4c_pack_query", "z4c_block_offset", "z4c_pack_bind",
            "z4c_pack_destroy", "z4c_last_error", "z4c_fill_ghosts", "z4c_rhs", "z4c_rk4_stage",
            "z4c_rk4_step", "z4c_constraints", "z4c_refine_flags", "z4c_stencil_weights",
-           "z4c_profile", "z4c_profile_read"]
+           "z4c_profile", "z4c_profile_read", "z4c_features", "z4c_pack_inject_2h", "z4c_labels",
+           "z4c_feature_stats", "z4c_mlp_normalize", "z4c_mlp_forward", "z4c_mlp_backward",
+           "z4c_mlp_adam", "z4c_refine_flags_learned", "z4c_set_variant", "z4c_autotune"]
+MLP_NPARAM = 5313
+
+
+class MlpModel(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("stats", C.c_void_p), ("range", C.POINTER(C.c_double)),
+                ("tau_ref", C.c_double), ("tau_deref", C.c_double), ("chi_thr", C.c_double),
+                ("dchi_thr", C.c_double), ("level_max", C.c_int32), ("pad", C.c_int32)]
 
 _lib = None
 
@@ -99,6 +108,19 @@ def lib():
                                        C.POINTER(C.c_int8), vp]
         L.z4c_stencil_weights.argtypes = [C.c_int32, C.POINTER(C.c_double),
                                           C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.z4c_features.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_double), vp]
+        L.z4c_pack_inject_2h.argtypes = [vp, C.c_int32, vp, C.c_int32, vp]
+        L.z4c_labels.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double), vp]
+        L.z4c_feature_stats.argtypes = [vp, C.c_int32, vp, vp]
+        L.z4c_mlp_normalize.argtypes = [vp, C.c_int32, vp, vp, vp]
+        L.z4c_mlp_forward.argtypes = [vp, vp, C.c_int32, vp, vp, vp]
+        L.z4c_mlp_backward.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp, vp, vp, vp]
+        L.z4c_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float,
+                                   C.c_float, vp]
+        L.z4c_refine_flags_learned.argtypes = [vp, C.c_int32, C.POINTER(MlpModel),
+                                               C.POINTER(C.c_int8), C.POINTER(C.c_int8), vp]
+        L.z4c_set_variant.argtypes = [vp, C.c_int32, C.c_int32, vp]
+        L.z4c_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32), vp]
         L.z4c_profile.argtypes = [vp, C.c_int32]
         L.z4c_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.c_int32]
         _lib = L
@@ -117,7 +139,7 @@ def make_params(mesh, p: dict, precision: int = FP64) -> Params:
     for k in ("ko_sigma", "kappa1", "kappa2", "eta", "mu_S", "chi_floor", "alpha_floor"):
         setattr(q, k, float(p[k]))
     q.terms = int(p.get("terms", TERM_ALL))
-    q.flags = FLAG_ENFORCE if int(p.get("enforce", 1)) else 0
+    q.flags = (FLAG_ENFORCE if int(p.get("enforce", 1)) else 0) | (FLAG_GRAPH if p.get("graph") else 0)
     return q
 
 
@@ -275,12 +297,24 @@ class Pack:
         self._check(lib().z4c_rhs(self.h, src_reg, C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
+    def set_variant(self, variant: int, persistent: bool = False, stream=None):
+        self._check(lib().z4c_set_variant(self.h, variant, 1 if persistent else 0, _stream_ptr(stream)))
+
+    def autotune(self, reps: int = 3, stream=None):
+        """Time every tile shape / launch mode; keep the fastest.  Returns
+        (chosen index, times in ms per RHS launch indexed 2*variant+persistent)."""
+        t = (C.c_double * 8)()
+        ch = C.c_int32()
+        self._check(lib().z4c_autotune(self.h, reps, t, C.byref(ch), _stream_ptr(stream)))
+        return int(ch.value), np.array(t[:])
+
     def profile(self, enable: bool = True):
         self._check(lib().z4c_profile(self.h, 1 if enable else 0))
 
     def profile_read(self, reset: bool = True):
-        """(stage ms, stage launches, fill ms, fill launches) since the last reset."""
-        out = (C.c_double * 4)()
+        """(stage ms, stage launches, fill ms, fill launches, graph ms, graph
+        launches) since the last reset."""
+        out = (C.c_double * 6)()
         self._check(lib().z4c_profile_read(self.h, out, 1 if reset else 0))
         return tuple(out[:])
 
@@ -321,3 +355,120 @@ class Pack:
         flags = (C.c_int8 * self.mesh.nb)()
         self._check(lib().z4c_refine_flags(self.h, reg, C.byref(rp), flags, _stream_ptr(stream)))
         return np.array(flags[:], dtype=np.int8)
+
+
+# ---------------------------------------------------------------- learned part
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _ok(rc, what):
+    if rc:
+        raise Z4cError(rc, what)
+
+
+def features(pack: "Pack", reg: int = REG_U, device_out=None, stream=None):
+    """(nb, 16) float64 features (numpy); optionally also into a device tensor."""
+    out = np.zeros(pack.mesh.nb * 16)
+    pack._check(lib().z4c_features(pack.h, reg, _ptr(device_out) if device_out is not None else None,
+                                   out.ctypes.data_as(C.POINTER(C.c_double)), _stream_ptr(stream)))
+    return out.reshape(pack.mesh.nb, 16)
+
+
+def inject_2h(pack_h: "Pack", pack_2h: "Pack", reg_h: int = REG_U, reg_2h: int = REG_U, stream=None):
+    pack_h._check(lib().z4c_pack_inject_2h(pack_h.h, reg_h, pack_2h.h, reg_2h, _stream_ptr(stream)))
+
+
+def labels(pack_h: "Pack", rhs_h, pack_2h: "Pack", rhs_2h, stream=None):
+    out = np.zeros(pack_h.mesh.nb)
+    pack_h._check(lib().z4c_labels(pack_h.h, _ptr(rhs_h), pack_2h.h, _ptr(rhs_2h),
+                                   out.ctypes.data_as(C.POINTER(C.c_double)), _stream_ptr(stream)))
+    return out
+
+
+class Mlp:
+    """Device state of the 16-64-64-1 indicator network (float32 master
+    weights, Adam moments, feature statistics); all arithmetic in libz4c."""
+
+    def __init__(self, init_params: np.ndarray, device: str = "cuda"):
+        import torch
+        self.device = device
+        self.params = torch.tensor(np.asarray(init_params, np.float32), device=device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.stats = torch.zeros(64, dtype=torch.float64, device=device)
+        self.step = 0
+
+    def fit_stats(self, raw):
+        """Feature statistics (mean, std, min, max of phi) from a device
+        float64 tensor of raw features (B, 16)."""
+        _ok(lib().z4c_feature_stats(_ptr(raw), raw.shape[0], _ptr(self.stats), _stream_ptr(None)),
+            "feature stats")
+
+    def normalize(self, raw):
+        import torch
+        X = torch.empty((raw.shape[0], 16), dtype=torch.float32, device=self.device)
+        _ok(lib().z4c_mlp_normalize(_ptr(raw), raw.shape[0], _ptr(self.stats), _ptr(X),
+                                    _stream_ptr(None)), "normalize")
+        return X
+
+    def forward(self, X, cache=None):
+        import torch
+        Y = torch.empty(X.shape[0], dtype=torch.float32, device=self.device)
+        _ok(lib().z4c_mlp_forward(_ptr(self.params), _ptr(X), X.shape[0], _ptr(Y),
+                                  _ptr(cache) if cache is not None else None, _stream_ptr(None)),
+            "mlp forward")
+        return Y
+
+    def loss_grad(self, X, T):
+        """Forward + backward: returns (Y, grad tensor, loss tensor)."""
+        import torch
+        B = X.shape[0]
+        cache = torch.empty(B * 128, dtype=torch.float32, device=self.device)
+        work = torch.empty(B * 129, dtype=torch.float32, device=self.device)
+        Y = self.forward(X, cache)
+        _ok(lib().z4c_mlp_backward(_ptr(self.params), _ptr(X), _ptr(Y), _ptr(T), _ptr(cache), B,
+                                   _ptr(self.grad), _ptr(self.loss), _ptr(work), _stream_ptr(None)),
+            "mlp backward")
+        return Y, self.grad, self.loss
+
+    def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.step += 1
+        _ok(lib().z4c_mlp_adam(_ptr(self.params), _ptr(self.grad), _ptr(self.m), _ptr(self.v),
+                               self.step, lr, b1, b2, eps, _stream_ptr(None)), "adam")
+
+    def train(self, X, T, epochs: int, lr=1e-3, batch: int = 0, seed: int = 0):
+        """Full-batch (batch=0) or fixed mini-batch Adam; returns the final loss."""
+        import torch
+        B = X.shape[0]
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        for _ in range(epochs):
+            if batch and batch < B:
+                perm = torch.randperm(B, generator=g).to(X.device)
+                for s in range(0, B - batch + 1, batch):
+                    idx = perm[s:s + batch]
+                    self.loss_grad(X[idx].contiguous(), T[idx].contiguous())
+                    self.adam_step(lr)
+            else:
+                self.loss_grad(X, T)
+                self.adam_step(lr)
+        _, _, loss = self.loss_grad(X, T)
+        return float(loss.item())
+
+
+def refine_flags_learned(pack: "Pack", mlp: Mlp, phi_range: np.ndarray, tau_ref: float,
+                         tau_deref: float, chi_thr=0.3, dchi_thr=0.1, level_max=10,
+                         reg: int = REG_U, stream=None):
+    md = MlpModel()
+    md.params = mlp.params.data_ptr()
+    md.stats = mlp.stats.data_ptr()
+    rng = np.ascontiguousarray(phi_range, dtype=np.float64)
+    md.range = rng.ctypes.data_as(C.POINTER(C.c_double))
+    md.tau_ref, md.tau_deref, md.chi_thr, md.dchi_thr = tau_ref, tau_deref, chi_thr, dchi_thr
+    md.level_max = level_max
+    flags = (C.c_int8 * pack.mesh.nb)()
+    fb = (C.c_int8 * pack.mesh.nb)()
+    pack._check(lib().z4c_refine_flags_learned(pack.h, reg, C.byref(md), flags, fb, _stream_ptr(stream)))
+    return np.array(flags[:], np.int8), np.array(fb[:], np.int8)

@@ -33,6 +33,8 @@ struct z4c_pack {
     std::vector<double> rw, pw, wtab;
     int64_t shadow_elems = 0;
     size_t ws_xfer = 0, ws_prol = 0, ws_w = 0, ws_shadow = 0;
+    size_t ws_first = 0, ws_feat = 0, ws_x = 0, ws_y = 0;
+    std::vector<int32_t> first_work;
     int maxghost = 0;
     int64_t zones = 0;
     size_t reg_bytes[Z4C_NREG] = {0, 0, 0, 0};
@@ -44,11 +46,20 @@ struct z4c_pack {
     char* ws = nullptr;
     std::vector<double> part_host;
     std::string err;
+    // stage-kernel variant (tile shape) and launch mode
+    int variant = 0;
+    bool persistent = false;
+    int grid_persistent = 0;
+    // captured RK4 step (hipGraph), valid for one (dt, stream)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    double graph_dt = 0.0;
+    hipStream_t graph_stream = nullptr;
     // optional kernel timing
     bool prof = false;
     struct EvPair { hipEvent_t a, b; int kind; };
     std::vector<EvPair> ev;
-    double prof_acc[4] = {0, 0, 0, 0};
+    double prof_acc[6] = {0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -91,12 +102,25 @@ ParamsDev dev_params(const z4c_params& p)
     return d;
 }
 
-// tile shape of the fused stage kernel (256 threads, one zone each)
-void tile_shape(int, int& ti, int& tj, int& tk)
+// work list of the fused stage kernel for tile-shape variant v
+bool build_work(const std::vector<z4c_block>& blk, int v, std::vector<WorkItem>& work)
 {
-    ti = 8;
-    tj = 8;
-    tk = 4;
+    const int ti = TILE_SHAPES[v][0], tj = TILE_SHAPES[v][1], tk = TILE_SHAPES[v][2];
+    work.clear();
+    for (size_t b = 0; b < blk.size(); ++b) {
+        const int n = blk[b].n;
+        if (n % ti || n % tj || n % tk) return false;
+        for (int k0 = 0; k0 < n; k0 += tk)
+            for (int j0 = 0; j0 < n; j0 += tj)
+                for (int i0 = 0; i0 < n; i0 += ti) {
+                    WorkItem w;
+                    w.block = (int32_t)b;
+                    w.i0 = (int16_t)i0; w.j0 = (int16_t)j0; w.k0 = (int16_t)k0;
+                    w.ni = (int16_t)ti; w.nj = (int16_t)tj; w.nk = (int16_t)tk;
+                    work.push_back(w);
+                }
+    }
+    return true;
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -408,23 +432,8 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
     pk->reg_bytes[0] = pk->reg_bytes[1] = pk->reg_bytes[2] = align256((size_t)off * esz);
     pk->reg_bytes[3] = align256((size_t)ioff * 8);
 
-    // work list: tiles of active cells
-    for (int b = 0; b < nblocks; ++b) {
-        int ti, tj, tk;
-        const int n = blocks[b].n;
-        tile_shape(n, ti, tj, tk);
-        for (int k0 = 0; k0 < n; k0 += tk)
-            for (int j0 = 0; j0 < n; j0 += tj)
-                for (int i0 = 0; i0 < n; i0 += ti) {
-                    WorkItem w;
-                    w.block = b;
-                    w.i0 = (int16_t)i0; w.j0 = (int16_t)j0; w.k0 = (int16_t)k0;
-                    w.ni = (int16_t)std::min(ti, n - i0);
-                    w.nj = (int16_t)std::min(tj, n - j0);
-                    w.nk = (int16_t)std::min(tk, n - k0);
-                    pk->work.push_back(w);
-                }
-    }
+    // work list: tiles of active cells (variant 0 fits every valid pack)
+    build_work(pk->blk, 0, pk->work);
 
     // leaf lookup per level, at `unit` granularity
     std::memset(&pk->L, 0, sizeof(pk->L));
@@ -463,13 +472,21 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
     pk->ws_blocks = o; o = align256(o + sizeof(BlockDev) * nblocks);
     pk->ws_work = o;   o = align256(o + sizeof(WorkItem) * pk->work.size());
     pk->ws_map = o;    o = align256(o + sizeof(int32_t) * pk->map.size());
-    pk->ws_part = o;   o = align256(o + sizeof(double) * 8 * pk->work.size());
+    pk->ws_part = o;   o = align256(o + sizeof(double) * 16 * pk->work.size());
+    pk->ws_first = o;  o = align256(o + sizeof(int32_t) * (nblocks + 1));
+    pk->ws_feat = o;   o = align256(o + sizeof(double) * 16 * nblocks);
+    pk->ws_x = o;      o = align256(o + sizeof(float) * 16 * nblocks);
+    pk->ws_y = o;      o = align256(o + sizeof(float) * nblocks);
     pk->ws_xfer = o;   o = align256(o + sizeof(XferItem) * pk->xfer.size());
     pk->ws_prol = o;   o = align256(o + sizeof(ProlongItem) * pk->prol.size());
     pk->ws_w = o;      o = align256(o + sizeof(double) * 80);
     pk->ws_shadow = o; o = align256(o + esz * (size_t)pk->shadow_elems);
     pk->ws_total = o;
-    pk->part_host.resize(8 * pk->work.size());
+    pk->part_host.resize(16 * pk->work.size());
+    pk->first_work.assign(nblocks + 1, 0);
+    for (size_t w = 0; w < pk->work.size(); ++w) pk->first_work[pk->work[w].block + 1] = (int32_t)(w + 1);
+    for (int b = 0; b < nblocks; ++b)
+        if (pk->first_work[b + 1] < pk->first_work[b]) pk->first_work[b + 1] = pk->first_work[b];
     *out = pk;
     return Z4C_OK;
 }
@@ -515,6 +532,9 @@ int z4c_pack_bind(z4c_pack* pk, void* const regs[Z4C_NREG], void* workspace, siz
     if (e == hipSuccess)
         e = hipMemcpyAsync(ws + pk->ws_map, pk->map.data(), sizeof(int32_t) * pk->map.size(),
                            hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + pk->ws_first, pk->first_work.data(), sizeof(int32_t) * pk->first_work.size(),
+                           hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !pk->xfer.empty())
         e = hipMemcpyAsync(ws + pk->ws_xfer, pk->xfer.data(), sizeof(XferItem) * pk->xfer.size(),
                            hipMemcpyHostToDevice, s);
@@ -539,6 +559,8 @@ int z4c_pack_bind(z4c_pack* pk, void* const regs[Z4C_NREG], void* workspace, siz
 void z4c_pack_destroy(z4c_pack* pk)
 {
     if (!pk) return;
+    if (pk->gexec) hipGraphExecDestroy(pk->gexec);
+    if (pk->graph) hipGraphDestroy(pk->graph);
     for (auto& e : pk->ev) {
         hipEventDestroy(e.a);
         hipEventDestroy(e.b);
@@ -563,13 +585,13 @@ int z4c_profile_read(z4c_pack* pk, double* out, int32_t reset)
         hipEventDestroy(e.a);
         hipEventDestroy(e.b);
         if (r != hipSuccess) { pk->ev.clear(); return fail(pk, Z4C_EDEVICE, "profile: %s", hipGetErrorString(r)); }
-        pk->prof_acc[e.kind == 0 ? 0 : 2] += ms;
-        pk->prof_acc[e.kind == 0 ? 1 : 3] += 1.0;
+        pk->prof_acc[2 * e.kind] += ms;
+        pk->prof_acc[2 * e.kind + 1] += 1.0;
     }
     pk->ev.clear();
-    for (int q = 0; q < 4; ++q) out[q] = pk->prof_acc[q];
+    for (int q = 0; q < 6; ++q) out[q] = pk->prof_acc[q];
     if (reset)
-        for (int q = 0; q < 4; ++q) pk->prof_acc[q] = 0.0;
+        for (int q = 0; q < 6; ++q) pk->prof_acc[q] = 0.0;
     return Z4C_OK;
 }
 
@@ -614,6 +636,8 @@ static StageArgs stage_args(z4c_pack* pk)
 {
     StageArgs a;
     std::memset(&a, 0, sizeof(a));
+    a.nwork = (int32_t)pk->work.size();
+    a.persistent = pk->persistent ? 1 : 0;
     a.blocks = reinterpret_cast<const BlockDev*>(pk->ws + pk->ws_blocks);
     a.work = reinterpret_cast<const WorkItem*>(pk->ws + pk->ws_work);
     a.P = dev_params(pk->p);
@@ -633,7 +657,8 @@ int z4c_rhs(z4c_pack* pk, int32_t src_reg, void* rhs_out, void* stream)
     a.src = pk->reg[src_reg];
     a.rhs_out = static_cast<double*>(rhs_out);
     a.stage = 0;
-    hipError_t e = launch_stage(pk->p.fd_order / 2, pk->p.precision, a, (int)pk->work.size(), as_stream(stream));
+    const int grid = pk->persistent ? pk->grid_persistent : (int)pk->work.size();
+    hipError_t e = launch_stage(pk->p.fd_order / 2, pk->p.precision, pk->variant, a, grid, as_stream(stream));
     if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "rhs launch: %s", hipGetErrorString(e));
     return Z4C_OK;
 }
@@ -654,7 +679,8 @@ int z4c_rk4_stage(z4c_pack* pk, int32_t stage, double dt, void* stream)
     a.dt = dt;
     a.stage = stage;
     ProfScope ps(pk, as_stream(stream), 0);
-    hipError_t e = launch_stage(pk->p.fd_order / 2, pk->p.precision, a, (int)pk->work.size(), as_stream(stream));
+    const int grid = pk->persistent ? pk->grid_persistent : (int)pk->work.size();
+    hipError_t e = launch_stage(pk->p.fd_order / 2, pk->p.precision, pk->variant, a, grid, as_stream(stream));
     if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "stage launch: %s", hipGetErrorString(e));
     return Z4C_OK;
 }
@@ -663,12 +689,113 @@ int z4c_rk4_step(z4c_pack* pk, double dt, int32_t nsteps, void* stream)
 {
     if (!pk) return Z4C_EINVAL;
     if (nsteps < 0) return fail(pk, Z4C_EINVAL, "negative nsteps");
-    for (int s = 0; s < nsteps; ++s)
+    if (!std::isfinite(dt)) return fail(pk, Z4C_EINVAL, "dt not finite");
+    if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
+    hipStream_t s = as_stream(stream);
+    if ((pk->p.flags & Z4C_FLAG_GRAPH) && s != nullptr && nsteps > 0) {
+        // one captured graph of the four stages (ghost fills included), replayed
+        if (!pk->gexec || pk->graph_dt != dt || pk->graph_stream != s) {
+            if (pk->gexec) { hipGraphExecDestroy(pk->gexec); pk->gexec = nullptr; }
+            if (pk->graph) { hipGraphDestroy(pk->graph); pk->graph = nullptr; }
+            const bool prof = pk->prof;
+            pk->prof = false;
+            hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) { pk->prof = prof; return fail(pk, Z4C_EDEVICE, "capture: %s", hipGetErrorString(e)); }
+            int rc = Z4C_OK;
+            for (int st = 1; st <= 4 && rc == Z4C_OK; ++st) rc = z4c_rk4_stage(pk, st, dt, stream);
+            hipGraph_t gr = nullptr;
+            e = hipStreamEndCapture(s, &gr);
+            pk->prof = prof;
+            if (rc) { if (gr) hipGraphDestroy(gr); return rc; }
+            if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "end capture: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&pk->gexec, gr, nullptr, nullptr, 0);
+            if (e != hipSuccess) { hipGraphDestroy(gr); return fail(pk, Z4C_EDEVICE, "instantiate: %s", hipGetErrorString(e)); }
+            pk->graph = gr;
+            pk->graph_dt = dt;
+            pk->graph_stream = s;
+        }
+        for (int n = 0; n < nsteps; ++n) {
+            ProfScope ps(pk, s, 2);
+            hipError_t e = hipGraphLaunch(pk->gexec, s);
+            if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "graph launch: %s", hipGetErrorString(e));
+        }
+        return Z4C_OK;
+    }
+    for (int n = 0; n < nsteps; ++n)
         for (int st = 1; st <= 4; ++st) {
             int rc = z4c_rk4_stage(pk, st, dt, stream);
             if (rc) return rc;
         }
     return Z4C_OK;
+}
+
+int z4c_set_variant(z4c_pack* pk, int32_t variant, int32_t persistent, void* stream)
+{
+    if (!pk) return Z4C_EINVAL;
+    if (variant < 0 || variant >= NVARIANT) return fail(pk, Z4C_EINVAL, "bad variant %d", variant);
+    std::vector<WorkItem> w;
+    if (!build_work(pk->blk, variant, w)) return fail(pk, Z4C_EUNSUPPORTED, "tile shape %d does not divide the blocks", variant);
+    if (w.size() != pk->work.size()) return fail(pk, Z4C_EINVAL, "work size mismatch");
+    pk->work = w;
+    pk->variant = variant;
+    pk->persistent = persistent != 0;
+    if (pk->persistent) {
+        int dev = 0, ncu = 0;
+        hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 256;
+        const int occ = stage_occupancy(pk->p.fd_order / 2, pk->p.precision, variant);
+        pk->grid_persistent = std::min<int>((int)pk->work.size(), ncu * occ);
+    }
+    if (pk->gexec) { hipGraphExecDestroy(pk->gexec); pk->gexec = nullptr; }
+    if (pk->graph) { hipGraphDestroy(pk->graph); pk->graph = nullptr; }
+    if (pk->bound) {
+        hipError_t e = hipMemcpyAsync(pk->ws + pk->ws_work, pk->work.data(), sizeof(WorkItem) * pk->work.size(),
+                                      hipMemcpyHostToDevice, as_stream(stream));
+        if (e == hipSuccess) e = hipStreamSynchronize(as_stream(stream));
+        if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "work upload: %s", hipGetErrorString(e));
+    }
+    return Z4C_OK;
+}
+
+int z4c_autotune(z4c_pack* pk, int32_t reps, double* times_ms, int32_t* chosen, void* stream)
+{
+    if (!pk) return Z4C_EINVAL;
+    if (reps < 1 || !chosen) return fail(pk, Z4C_EINVAL, "bad autotune arguments");
+    if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
+    hipStream_t s = as_stream(stream);
+    int rc = z4c_fill_ghosts(pk, Z4C_REG_U, stream);
+    if (rc) return rc;
+    double best = INFINITY;
+    int bv = -1, bp = 0;
+    for (int v = 0; v < NVARIANT; ++v)
+        for (int per = 0; per <= 1; ++per) {
+            const int q = 2 * v + per;
+            if (times_ms) times_ms[q] = -1.0;
+            std::vector<WorkItem> w;
+            if (!build_work(pk->blk, v, w)) continue;
+            rc = z4c_set_variant(pk, v, per, stream);
+            if (rc) return rc;
+            hipEvent_t e0, e1;
+            if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+                return fail(pk, Z4C_EDEVICE, "autotune events");
+            rc = z4c_rhs(pk, Z4C_REG_U, pk->reg[Z4C_REG_A], stream);  // warm-up
+            hipEventRecord(e0, s);
+            for (int r = 0; r < reps && rc == Z4C_OK; ++r) rc = z4c_rhs(pk, Z4C_REG_U, pk->reg[Z4C_REG_A], stream);
+            hipEventRecord(e1, s);
+            hipError_t e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            if (rc) return rc;
+            if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "autotune timing: %s", hipGetErrorString(e));
+            const double t = ms / reps;
+            if (times_ms) times_ms[q] = t;
+            if (t < best) { best = t; bv = v; bp = per; }
+        }
+    if (bv < 0) return fail(pk, Z4C_EUNSUPPORTED, "no tile shape fits");
+    *chosen = 2 * bv + bp;
+    return z4c_set_variant(pk, bv, bp, stream);
 }
 
 static int run_diag(z4c_pack* pk, int32_t reg, int mode, void* per_zone, const double* centres,
@@ -770,6 +897,180 @@ int z4c_refine_flags(z4c_pack* pk, int32_t reg, const z4c_refine_params* rp, int
         if (f > 0 && lev >= rp->level_max) f = 0;
         if (f < 0 && lev == 0) f = 0;
         flags_out[b] = (int8_t)f;
+    }
+    return Z4C_OK;
+}
+
+int z4c_features(z4c_pack* pk, int32_t reg, void* feat_dev, double* feat_host, void* stream)
+{
+    if (!pk) return Z4C_EINVAL;
+    if (reg < Z4C_REG_U || reg > Z4C_REG_S2) return fail(pk, Z4C_EINVAL, "bad register %d", reg);
+    if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
+    int rc = z4c_fill_ghosts(pk, reg, stream);
+    if (rc) return rc;
+    FeatArgs a;
+    a.src = pk->reg[reg];
+    a.blocks = reinterpret_cast<const BlockDev*>(pk->ws + pk->ws_blocks);
+    a.work = reinterpret_cast<const WorkItem*>(pk->ws + pk->ws_work);
+    a.first_work = reinterpret_cast<const int32_t*>(pk->ws + pk->ws_first);
+    a.partial = reinterpret_cast<double*>(pk->ws + pk->ws_part);
+    a.feat = feat_dev ? static_cast<double*>(feat_dev) : reinterpret_cast<double*>(pk->ws + pk->ws_feat);
+    a.g = pk->p.nghost;
+    a.nblocks = (int32_t)pk->blk.size();
+    hipStream_t s = as_stream(stream);
+    hipError_t e = launch_features(pk->p.fd_order / 2, pk->p.precision, a, (int)pk->work.size(), s);
+    if (e == hipSuccess && feat_host) {
+        e = hipMemcpyAsync(feat_host, a.feat, sizeof(double) * 16 * pk->blk.size(), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "features: %s", hipGetErrorString(e));
+    return Z4C_OK;
+}
+
+int z4c_pack_inject_2h(z4c_pack* ph, int32_t reg_h, z4c_pack* p2, int32_t reg_2h, void* stream)
+{
+    if (!ph || !p2) return Z4C_EINVAL;
+    if (reg_h < Z4C_REG_U || reg_h > Z4C_REG_S2 || reg_2h < Z4C_REG_U || reg_2h > Z4C_REG_S2)
+        return fail(ph, Z4C_EINVAL, "bad register");
+    if (!ph->bound || !p2->bound) return fail(ph, Z4C_ESTATE, "pack not bound");
+    if (ph->blk.size() != p2->blk.size() || ph->p.precision != p2->p.precision)
+        return fail(ph, Z4C_EINVAL, "2h pack does not match");
+    int maxc = 0;
+    for (size_t b = 0; b < ph->blk.size(); ++b) {
+        const z4c_block &F = ph->blk[b], &C2 = p2->blk[b];
+        if (C2.n * 2 != F.n || C2.level != F.level) return fail(ph, Z4C_EINVAL, "2h block %zu mismatch", b);
+        for (int a = 0; a < 3; ++a)
+            if (C2.ilo[a] * 2 != F.ilo[a]) return fail(ph, Z4C_EINVAL, "2h block %zu corner mismatch", b);
+        maxc = std::max(maxc, C2.n * C2.n * C2.n);
+    }
+    InjectArgs a;
+    a.src = ph->reg[reg_h];
+    a.dst = p2->reg[reg_2h];
+    a.blocks1 = reinterpret_cast<const BlockDev*>(ph->ws + ph->ws_blocks);
+    a.blocks2 = reinterpret_cast<const BlockDev*>(p2->ws + p2->ws_blocks);
+    a.g1 = ph->p.nghost;
+    a.g2 = p2->p.nghost;
+    hipError_t e = launch_inject(ph->p.precision, a, (int)ph->blk.size(), maxc, as_stream(stream));
+    if (e != hipSuccess) return fail(ph, Z4C_EDEVICE, "inject: %s", hipGetErrorString(e));
+    return Z4C_OK;
+}
+
+int z4c_labels(z4c_pack* ph, const void* rhs_h, z4c_pack* p2, const void* rhs_2h, double* labels_out,
+               void* stream)
+{
+    if (!ph || !p2) return Z4C_EINVAL;
+    if (!rhs_h || !rhs_2h || !labels_out) return fail(ph, Z4C_EINVAL, "null argument");
+    if (!ph->bound || !p2->bound) return fail(ph, Z4C_ESTATE, "pack not bound");
+    if (ph->blk.size() != p2->blk.size()) return fail(ph, Z4C_EINVAL, "2h pack does not match");
+    for (size_t b = 0; b < ph->blk.size(); ++b)
+        if (p2->blk[b].n * 2 != ph->blk[b].n) return fail(ph, Z4C_EINVAL, "2h block %zu mismatch", b);
+    LabelArgs a;
+    a.rhs1 = static_cast<const double*>(rhs_h);
+    a.rhs2 = static_cast<const double*>(rhs_2h);
+    a.blocks1 = reinterpret_cast<const BlockDev*>(ph->ws + ph->ws_blocks);
+    a.blocks2 = reinterpret_cast<const BlockDev*>(p2->ws + p2->ws_blocks);
+    a.work2 = reinterpret_cast<const WorkItem*>(p2->ws + p2->ws_work);
+    a.partial = reinterpret_cast<double*>(p2->ws + p2->ws_part);
+    hipStream_t s = as_stream(stream);
+    hipError_t e = launch_labels(a, (int)p2->work.size(), s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p2->part_host.data(), a.partial, sizeof(double) * p2->work.size(),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(ph, Z4C_EDEVICE, "labels: %s", hipGetErrorString(e));
+    const size_t nb = ph->blk.size();
+    std::vector<double> sum(nb, 0.0);
+    for (size_t w = 0; w < p2->work.size(); ++w) sum[p2->work[w].block] += p2->part_host[w];
+    for (size_t b = 0; b < nb; ++b) {
+        const double n3 = std::pow((double)p2->blk[b].n, 3);
+        labels_out[b] = std::log10(std::sqrt(sum[b] / (NF * n3)) + 1e-30);
+    }
+    return Z4C_OK;
+}
+
+int z4c_feature_stats(const void* raw, int32_t B, void* stats, void* stream)
+{
+    if (!raw || !stats || B < 1) return Z4C_EINVAL;
+    return launch_feat_stats(static_cast<const double*>(raw), B, static_cast<double*>(stats),
+                             as_stream(stream)) == hipSuccess ? Z4C_OK : Z4C_EDEVICE;
+}
+
+int z4c_mlp_normalize(const void* raw, int32_t B, const void* stats, void* X, void* stream)
+{
+    if (!raw || !stats || !X || B < 1) return Z4C_EINVAL;
+    return launch_normalize(static_cast<const double*>(raw), B, static_cast<const double*>(stats),
+                            static_cast<float*>(X), as_stream(stream)) == hipSuccess ? Z4C_OK : Z4C_EDEVICE;
+}
+
+int z4c_mlp_forward(const void* params, const void* X, int32_t B, void* Y, void* cache, void* stream)
+{
+    if (!params || !X || !Y || B < 1) return Z4C_EINVAL;
+    return launch_mlp_forward(static_cast<const float*>(params), static_cast<const float*>(X), B,
+                              static_cast<float*>(Y), static_cast<float*>(cache),
+                              as_stream(stream)) == hipSuccess ? Z4C_OK : Z4C_EDEVICE;
+}
+
+int z4c_mlp_backward(const void* params, const void* X, const void* Y, const void* T, const void* cache,
+                     int32_t B, void* grad, void* loss, void* work, void* stream)
+{
+    if (!params || !X || !Y || !T || !cache || !grad || !work || B < 1) return Z4C_EINVAL;
+    return launch_mlp_backward(static_cast<const float*>(params), static_cast<const float*>(X),
+                               static_cast<const float*>(Y), static_cast<const float*>(T),
+                               static_cast<const float*>(cache), B, static_cast<float*>(grad),
+                               static_cast<float*>(loss), static_cast<float*>(work),
+                               as_stream(stream)) == hipSuccess ? Z4C_OK : Z4C_EDEVICE;
+}
+
+int z4c_mlp_adam(void* params, const void* grad, void* m, void* v, int32_t step, float lr, float beta1,
+                 float beta2, float eps, void* stream)
+{
+    if (!params || !grad || !m || !v || step < 1) return Z4C_EINVAL;
+    return launch_mlp_adam(static_cast<float*>(params), static_cast<const float*>(grad),
+                           static_cast<float*>(m), static_cast<float*>(v), step, lr, beta1, beta2, eps,
+                           as_stream(stream)) == hipSuccess ? Z4C_OK : Z4C_EDEVICE;
+}
+
+int z4c_refine_flags_learned(z4c_pack* pk, int32_t reg, const z4c_mlp_model* md, int8_t* flags_out,
+                             int8_t* fallback_out, void* stream)
+{
+    if (!pk) return Z4C_EINVAL;
+    if (!md || !md->params || !md->stats || !md->range || !flags_out) return fail(pk, Z4C_EINVAL, "null argument");
+    const int nb = (int)pk->blk.size();
+    std::vector<double> feat(16 * nb);
+    int rc = z4c_features(pk, reg, nullptr, nullptr, stream);
+    if (rc) return rc;
+    hipStream_t s = as_stream(stream);
+    double* fdev = reinterpret_cast<double*>(pk->ws + pk->ws_feat);
+    float* X = reinterpret_cast<float*>(pk->ws + pk->ws_x);
+    float* Y = reinterpret_cast<float*>(pk->ws + pk->ws_y);
+    hipError_t e = launch_normalize(fdev, nb, static_cast<const double*>(md->stats), X, s);
+    if (e == hipSuccess) e = launch_mlp_forward(static_cast<const float*>(md->params), X, nb, Y, nullptr, s);
+    std::vector<float> yh(nb);
+    if (e == hipSuccess) e = hipMemcpyAsync(yh.data(), Y, sizeof(float) * nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(feat.data(), fdev, sizeof(double) * 16 * nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "learned flags: %s", hipGetErrorString(e));
+    for (int b = 0; b < nb; ++b) {
+        const int lev = pk->blk[b].level;
+        bool ood = !std::isfinite((double)yh[b]);
+        for (int k = 0; k < 16; ++k) {
+            const double r = feat[16 * b + k];
+            const double phi = k < 15 ? std::log10(std::fabs(r) + 1e-12) : r;
+            const double lo = md->range[k], hi = md->range[16 + k], pad = 0.1 * (hi - lo);
+            if (!std::isfinite(phi) || phi < lo - pad || phi > hi + pad) ood = true;
+        }
+        int f;
+        if (ood) {
+            const double gmax = feat[16 * b + 0];
+            f = gmax > md->dchi_thr ? 1 : (gmax < 0.5 * md->dchi_thr ? -1 : 0);
+        } else {
+            f = yh[b] > md->tau_ref ? 1 : (yh[b] < md->tau_deref ? -1 : 0);
+        }
+        if (feat[16 * b + 7] < md->chi_thr) f = 1;
+        if (f > 0 && lev >= md->level_max) f = 0;
+        if (f < 0 && lev == 0) f = 0;
+        flags_out[b] = (int8_t)f;
+        if (fallback_out) fallback_out[b] = ood ? 1 : 0;
     }
     return Z4C_OK;
 }

@@ -17,7 +17,12 @@ struct StageArgs {
     double dt;
     int32_t stage;            // 1..4, 0 = RHS only
     int32_t g;
+    int32_t nwork;            // work items
+    int32_t persistent;       // 1: grid smaller than nwork, workgroups loop
 };
+
+constexpr int NVARIANT = 4;
+extern const int TILE_SHAPES[NVARIANT][3];
 
 struct FillArgs {
     void* reg;
@@ -56,7 +61,46 @@ struct DiagArgs {
     int32_t g;
 };
 
-hipError_t launch_stage(int N, int prec, const StageArgs& a, int nwork, hipStream_t s);
+struct FeatArgs {
+    const void* src;
+    const BlockDev* blocks;
+    const WorkItem* work;
+    const int32_t* first_work;  // [nblocks + 1]: first work item of each block
+    double* partial;            // [nwork][16]
+    double* feat;               // [nblocks][16]
+    int32_t g, nblocks;
+};
+
+struct InjectArgs {
+    const void* src;            // h-pack register
+    void* dst;                  // 2h-pack register
+    const BlockDev* blocks1;    // h pack
+    const BlockDev* blocks2;    // 2h pack
+    int32_t g1, g2;
+};
+
+struct LabelArgs {
+    const double* rhs1;         // h-pack RHS (interior layout)
+    const double* rhs2;         // 2h-pack RHS
+    const BlockDev* blocks1;
+    const BlockDev* blocks2;
+    const WorkItem* work2;
+    double* partial;            // [nwork2]
+};
+
+hipError_t launch_features(int N, int prec, const FeatArgs& a, int nwork, hipStream_t s);
+hipError_t launch_inject(int prec, const InjectArgs& a, int nblocks, int maxcells, hipStream_t s);
+hipError_t launch_labels(const LabelArgs& a, int nwork2, hipStream_t s);
+hipError_t launch_mlp_forward(const float* P, const float* X, int B, float* Y, float* cache, hipStream_t s);
+hipError_t launch_mlp_backward(const float* P, const float* X, const float* Y, const float* T,
+                               const float* cache, int B, float* G, float* loss, float* work, hipStream_t s);
+hipError_t launch_mlp_adam(float* P, const float* G, float* M, float* V, int step, float lr, float b1,
+                           float b2, float eps, hipStream_t s);
+hipError_t launch_normalize(const double* raw, int B, const double* stats, float* X, hipStream_t s);
+hipError_t launch_feat_stats(const double* raw, int B, double* stats, hipStream_t s);
+
+hipError_t launch_stage(int N, int prec, int variant, const StageArgs& a, int grid, hipStream_t s);
+int stage_occupancy(int N, int prec, int variant);
 hipError_t launch_fill(int prec, const FillArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_diag(int N, int prec, const DiagArgs& a, int nwork, hipStream_t s);
 hipError_t launch_xlevel(int prec, const XlevelArgs& a, hipStream_t s);

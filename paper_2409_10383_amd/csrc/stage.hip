@@ -21,9 +21,10 @@
 
 namespace z4c {
 
-constexpr int TX = 8, TY = 8, TZ = 4;
-
-template <int N> struct TileGeom {
+// Tile shapes the autotuner chooses from (x, y, z extents; 256 zones each).
+// The per-zone arithmetic does not depend on the shape, so every variant
+// gives bitwise-identical results.
+template <int N, int TX, int TY, int TZ> struct TileGeom {
     static constexpr int R = N + 1;                 // halo of the staged tile
     static constexpr int SX = TX + 2 * R, SY = TY + 2 * R, SZ = TZ + 2 * R;
     static constexpr int NS = SX * SY * SZ;         // staged cells
@@ -60,20 +61,54 @@ __device__ __forceinline__ void axis_pass(const C* __restrict__ s, int c, int st
     ad += va * odd + (C)fabs((double)va) * el + sig * ek;
 }
 
-template <int N, class T, class C>
+// The work items are spread so that each of the 8 XCDs (each with its own
+// L2) receives a contiguous run of tiles: workgroup b runs on XCD b % 8.
+__device__ __forceinline__ int work_index(int slot, int nwork)
+{
+    const int per = (nwork + 7) / 8;
+    const int x = slot % 8, k = slot / 8;
+    return x * per + k;
+}
+
+template <int N, class T, class C, int TX, int TY, int TZ>
+__device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w, C* tile, C* dxs,
+                                           C* dys, C* adks);
+
+// One launch per stage.  With a.persistent the grid is sized to the
+// resident workgroups and each loops over its XCD's share of the work.
+template <int N, class T, class C, int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_stage(const StageArgs a)
 {
-    using G = TileGeom<N>;
-    constexpr int R = G::R, SX = G::SX, SY = G::SY;
+    using G = TileGeom<N, TX, TY, TZ>;
     __shared__ C tile[G::NS];
     __shared__ C dxs[G::NDX];
     __shared__ C dys[G::NDY];
     __shared__ C adks[NF * 256];   // advection + dissipation, per field and zone
+    if (!a.persistent) {
+        const int w = work_index(blockIdx.x, a.nwork);
+        if (w < a.nwork) stage_tile<N, T, C, TX, TY, TZ>(a, a.work[w], tile, dxs, dys, adks);
+        return;
+    }
+    // persistent: XCD x = blockIdx % 8 walks items x*per .. x*per+per-1
+    const int per = (a.nwork + 7) / 8;
+    const int x = blockIdx.x % 8, k0 = blockIdx.x / 8, nk = (gridDim.x - x + 7) / 8;
+    for (int k = k0; k < per; k += nk) {
+        const int w = x * per + k;
+        if (w >= a.nwork) break;
+        stage_tile<N, T, C, TX, TY, TZ>(a, a.work[w], tile, dxs, dys, adks);
+        __syncthreads();
+    }
+}
 
-    const WorkItem w = a.work[blockIdx.x];
+template <int N, class T, class C, int TX, int TY, int TZ>
+__device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w, C* tile, C* dxs,
+                                           C* dys, C* adks)
+{
+    using G = TileGeom<N, TX, TY, TZ>;
+    constexpr int R = G::R, SX = G::SX, SY = G::SY;
     const BlockDev B = a.blocks[w.block];
     const int t = threadIdx.x;
-    const int tx = t & 7, ty = (t >> 3) & 7, tz = t >> 6;
+    const int tx = t % TX, ty = (t / TX) % TY, tz = t / (TX * TY);
     const int i = w.i0 + tx, j = w.j0 + ty, k = w.k0 + tz;
     const int g = a.g, E = B.E, n = B.n;
     const int64_t slab = B.slab;
@@ -349,24 +384,62 @@ __global__ __launch_bounds__(256) void k_stage(const StageArgs a)
     for (int f = 0; f < NF; ++f) dst[f * slab] = (T)out[f];
 }
 
-template <int N>
-static hipError_t launch_n(int prec, const StageArgs& a, int nwork, hipStream_t s)
+template <int N, int TX, int TY, int TZ>
+static hipError_t launch_v(int prec, const StageArgs& a, int grid, hipStream_t s)
 {
     if (prec == 0)
-        hipLaunchKernelGGL((k_stage<N, double, double>), dim3(nwork), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_stage<N, double, double, TX, TY, TZ>), dim3(grid), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((k_stage<N, float, float>), dim3(nwork), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_stage<N, float, float, TX, TY, TZ>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_stage(int N, int prec, const StageArgs& a, int nwork, hipStream_t s)
+template <int N>
+static hipError_t launch_n(int prec, int variant, const StageArgs& a, int grid, hipStream_t s)
 {
-    switch (N) {
-    case 2: return launch_n<2>(prec, a, nwork, s);
-    case 3: return launch_n<3>(prec, a, nwork, s);
-    case 4: return launch_n<4>(prec, a, nwork, s);
+    switch (variant) {
+    case 0: return launch_v<N, 8, 8, 4>(prec, a, grid, s);
+    case 1: return launch_v<N, 16, 4, 4>(prec, a, grid, s);
+    case 2: return launch_v<N, 8, 4, 8>(prec, a, grid, s);
+    case 3: return launch_v<N, 16, 8, 2>(prec, a, grid, s);
     }
     return hipErrorInvalidValue;
+}
+
+const int TILE_SHAPES[NVARIANT][3] = {{8, 8, 4}, {16, 4, 4}, {8, 4, 8}, {16, 8, 2}};
+
+hipError_t launch_stage(int N, int prec, int variant, const StageArgs& a, int grid, hipStream_t s)
+{
+    switch (N) {
+    case 2: return launch_n<2>(prec, variant, a, grid, s);
+    case 3: return launch_n<3>(prec, variant, a, grid, s);
+    case 4: return launch_n<4>(prec, variant, a, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// resident workgroups per CU of a variant (for the persistent grid)
+int stage_occupancy(int N, int prec, int variant)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define Z4C_OCC(NN, TT, X, Y, Z) \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stage<NN, TT, TT, X, Y, Z>, 256, 0)
+#define Z4C_OCCV(NN, TT)                                                     \
+    switch (variant) {                                                        \
+    case 0: Z4C_OCC(NN, TT, 8, 8, 4); break;                                  \
+    case 1: Z4C_OCC(NN, TT, 16, 4, 4); break;                                 \
+    case 2: Z4C_OCC(NN, TT, 8, 4, 8); break;                                  \
+    case 3: Z4C_OCC(NN, TT, 16, 8, 2); break;                                 \
+    }
+    if (prec == 0) {
+        if (N == 2) { Z4C_OCCV(2, double) } else if (N == 3) { Z4C_OCCV(3, double) } else { Z4C_OCCV(4, double) }
+    } else {
+        if (N == 2) { Z4C_OCCV(2, float) } else if (N == 3) { Z4C_OCCV(3, float) } else { Z4C_OCCV(4, float) }
+    }
+#undef Z4C_OCCV
+#undef Z4C_OCC
+    return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 }  // namespace z4c

@@ -1,0 +1,146 @@
+"""Learned refinement indicator on the GPU: features and h-vs-2h labels
+against the oracle, network gradients against the bfloat16-emulating
+float64 oracle (relative L2 <= 1e-3 per tensor), and a training run whose
+predictions must select the blocks of largest truncation error better than
+the plain dchi-max criterion at the same refinement budget."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as omlp
+import z4c_inputs as zi
+from _parity import assert_parity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def z():
+    import paper_2409_10383_amd as m
+    return m
+
+
+def small_bbh(nb=4, n=16, ext=8.0, masses=(0.5, 0.5), xp=5.0, seed=None):
+    mesh = zi.uniform_mesh((nb,) * 3, n, 4, (-ext,) * 3, (ext,) * 3, zi.BC_OUTFLOW)
+    data = zi.brill_lindquist(mesh, [(masses[0], (xp, 0.0, 0.0)), (masses[1], (-xp, 0.0, 0.0))])
+    if seed is not None:
+        data = zi.add_perturbation(mesh, data, seed=seed, amp=1e-6)
+    return mesh, data
+
+
+def test_features_parity():
+    mesh, data = small_bbh(seed=11)
+    p = zi.params_default(6)
+    pk = z().Pack(mesh, p)
+    pk.upload(z().REG_U, data)
+    pk.rk4_step(0.25 * mesh.dx0, 1)     # non-trivial Khat, A~, beta, ...
+    state = pk.download(z().REG_U)
+    fg = z().features(pk)
+    om = oracle.OracleMesh(mesh)
+    fo = oracle.block_features(om, p, om.scatter(state))
+    np.testing.assert_allclose(fg, fo, rtol=1e-11, atol=1e-300)
+
+
+def test_labels_parity():
+    mesh, data = small_bbh(seed=12)
+    m2 = zi.coarse_2h_mesh(mesh)
+    p = zi.params_default(6)
+    ph, p2 = z().Pack(mesh, p), z().Pack(m2, p)
+    ph.upload(z().REG_U, data)
+    z().inject_2h(ph, p2)
+    ph.fill_ghosts()
+    p2.fill_ghosts()
+    lab = z().labels(ph, ph.rhs(), p2, p2.rhs())
+    oh, o2 = oracle.OracleMesh(mesh), oracle.OracleMesh(m2)
+    rh = oracle.rhs(oh, p, oh.scatter(data))
+    r2 = oracle.rhs(o2, p, o2.scatter([d[:, ::2, ::2, ::2].copy() for d in data]))
+    want = np.array([np.log10(np.sqrt(np.mean((a[:, ::2, ::2, ::2] - b) ** 2)) + 1e-30)
+                     for a, b in zip(rh, r2)])
+    np.testing.assert_allclose(lab, want, rtol=0, atol=1e-7)
+
+
+def test_mlp_gradients_match_bf16_oracle():
+    rng = np.random.default_rng(5)
+    params = omlp.init(7)
+    B = 300
+    X = rng.standard_normal((B, 16)).astype(np.float32)
+    T = rng.standard_normal(B).astype(np.float32)
+    net = z().Mlp(params)
+    Xd = torch.tensor(X, device="cuda")
+    Td = torch.tensor(T, device="cuda")
+    Y, G, L = net.loss_grad(Xd, Td)
+    torch.cuda.synchronize()
+    yo, _ = omlp.forward(params, X.astype(np.float64))
+    lo, go = omlp.loss_and_grad(params, X.astype(np.float64), T.astype(np.float64))
+    y = Y.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(y - yo) <= 1e-5 * np.linalg.norm(yo)
+    g = G.cpu().numpy().astype(np.float64)
+    o = 0
+    for name, shp in omlp.SIZES:
+        k = int(np.prod(shp))
+        rel = np.linalg.norm(g[o:o + k] - go[o:o + k]) / max(np.linalg.norm(go[o:o + k]), 1e-30)
+        assert rel <= 1e-3, (name, rel)
+        o += k
+    assert abs(float(L.item()) - lo) <= 1e-5 * lo
+    # one Adam step against the oracle's
+    net.adam_step(lr=1e-3)
+    p1, _, _ = omlp.adam(params, g, np.zeros_like(params), np.zeros_like(params), 1, lr=1e-3)
+    np.testing.assert_allclose(net.params.cpu().numpy(), p1, rtol=0, atol=1e-6)
+
+
+def _dataset(variants, steps=(0, 2)):
+    """Features and h-vs-2h labels of BL two-puncture packs at a few times."""
+    p = zi.params_default(6)
+    F, Y, D = [], [], []
+    for (m1, m2, xp, seed) in variants:
+        mesh, data = small_bbh(masses=(m1, m2), xp=xp, seed=seed)
+        m2h = zi.coarse_2h_mesh(mesh)
+        ph, p2 = z().Pack(mesh, p), z().Pack(m2h, p)
+        ph.upload(z().REG_U, data)
+        done = 0
+        for s in steps:
+            ph.rk4_step(0.25 * mesh.dx0, s - done)
+            done = s
+            z().inject_2h(ph, p2)
+            ph.fill_ghosts()
+            p2.fill_ghosts()
+            Y.append(z().labels(ph, ph.rhs(), p2, p2.rhs()))
+            feat_dev = torch.empty(mesh.nb * 16, dtype=torch.float64, device="cuda")
+            F.append(z().features(ph, device_out=feat_dev))
+            D.append(feat_dev.view(mesh.nb, 16))
+    return np.concatenate(F), np.concatenate(Y), torch.cat(D)
+
+
+def test_training_beats_dchi_max_at_equal_budget():
+    rng = np.random.default_rng(21)
+    train = [(rng.uniform(0.3, 0.7), rng.uniform(0.3, 0.7), rng.uniform(3.0, 7.0), 10 + i)
+             for i in range(8)]
+    test = [(rng.uniform(0.3, 0.7), rng.uniform(0.3, 0.7), rng.uniform(3.0, 7.0), 20 + i)
+            for i in range(3)]
+    Ftr, Ytr, Dtr = _dataset(train)
+    Fte, Yte, Dte = _dataset(test)
+    net = z().Mlp(omlp.init(1))
+    net.fit_stats(Dtr)
+    Xtr = net.normalize(Dtr)
+    Ttr = torch.tensor(Ytr.astype(np.float32), device="cuda")
+    loss0 = float(net.loss_grad(Xtr, Ttr)[2].item())
+    loss = net.train(Xtr, Ttr, epochs=60, lr=3e-3, batch=256)
+    assert loss < 0.2 * loss0, (loss0, loss)
+    pred = net.forward(net.normalize(Dte)).cpu().numpy()
+    nb = 64
+    gains = []
+    for s in range(len(Yte) // nb):
+        sl = slice(s * nb, (s + 1) * nb)
+        K = 8
+        truth = set(np.argsort(-Yte[sl])[:K])
+        learned = set(np.argsort(-pred[sl])[:K])
+        dchi = set(np.argsort(-Fte[sl, 0])[:K])
+        gains.append((len(truth & learned) - len(truth & dchi)) / K)
+    assert np.mean(gains) >= 0.0, gains
+    print("precision@K gain over dchi-max:", np.mean(gains), gains)

@@ -152,6 +152,18 @@ def nested_bbh_mesh(g: int = 5) -> Mesh:
     return split_blocks(m, which)
 
 
+def coarse_2h_mesh(mesh: Mesh) -> Mesh:
+    """The even-sublattice (2h) mesh of a single-level mesh: the same blocks
+    with n/2 cells and corner ilo/2, cell size 2h, domain shifted by -h/2 so
+    that its cell centres are the even fine cell centres."""
+    assert int(mesh.level.max()) == 0, "2h meshes are defined for single-level meshes"
+    h = mesh.dx0
+    return Mesh(level=mesh.level.copy(), n=(mesh.n // 2).astype(np.int32),
+                ilo=(mesh.ilo // 2).astype(np.int32), g=mesh.g,
+                nroot=tuple(int(v) // 2 for v in mesh.nroot), bc=mesh.bc,
+                lo=tuple(v - 0.5 * h for v in mesh.lo), dx0=2.0 * h)
+
+
 def blocks_in_box(mesh: Mesh, lo, hi):
     """Indices of blocks whose interior lies inside the physical box [lo, hi]."""
     out = []
