@@ -42,16 +42,9 @@ def pack(p) -> np.ndarray:
 
 
 def init(seed: int = 0) -> np.ndarray:
-    """He-uniform weights, zero biases (float32-representable values)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    p = {}
-    for name, shp in SIZES:
-        if name.startswith("W"):
-            lim = np.sqrt(6.0 / shp[1])
-            p[name] = rng.uniform(-lim, lim, size=shp)
-        else:
-            p[name] = np.zeros(shp)
-    return pack(p).astype(np.float32).astype(np.float64)
+    """Seeded initial weights (the shared input generator's)."""
+    import z4c_inputs
+    return z4c_inputs.mlp_init(seed)
 
 
 def forward(flat, X, emulate_bf16: bool = True):

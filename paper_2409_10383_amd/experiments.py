@@ -1,0 +1,128 @@
+"""Reports of the two extensions that change the method's numbers.
+
+  python -m paper_2409_10383_amd.experiments precision [--steps 100]
+      512 x 32^3 Brill-Lindquist + perturbations (dx = 0.125, 6th order):
+      FP32 storage vs FP64 after n RK4 steps, per-field relative L2 / Linf
+      errors and the Hamiltonian-constraint L2 (full and excised r >= 2).
+  python -m paper_2409_10383_amd.experiments learned
+      4096 x 16^3 two-puncture pack: train the indicator on h-vs-2h labels of
+      varied puncture setups and report flag agreement against dchi-max.
+
+Each prints one JSON object.  All arithmetic runs in libz4c.
+"""
+import argparse
+import json
+import sys
+
+import numpy as np
+
+
+def precision(steps: int):
+    import torch
+    import paper_2409_10383_amd as z4c
+    import z4c_inputs as zi
+    mesh, p, data, dt, _ = zi.workload("bl512x32")
+    res = {}
+    states = {}
+    for prec, name in ((z4c.FP64, "fp64"), (z4c.FP32_MIXED, "fp32")):
+        pk = z4c.Pack(mesh, p, prec)
+        pk.upload(z4c.REG_U, data)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        pk.rk4_step(dt, steps)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        _, nf = pk.constraints(per_zone=False)
+        _, ne = pk.constraints(per_zone=False, exclude=[(0.0, 0.0, 0.0)], r_exc=2.0)
+        res[name] = {"zcps": pk.zones * steps / (ms * 1e-3), "H_L2": nf[0], "H_L2_excised": ne[0],
+                     "M_L2": nf[2]}
+        states[name] = pk.download(z4c.REG_U)
+        del pk
+        torch.cuda.empty_cache()
+    err = {}
+    for f in range(22):
+        num2 = den2 = numi = deni = 0.0
+        for a, b in zip(states["fp32"], states["fp64"]):
+            d = a[f] - b[f]
+            num2 += float(np.sum(d * d))
+            den2 += float(np.sum(b[f] * b[f]))
+            numi = max(numi, float(np.abs(d).max()))
+            deni = max(deni, float(np.abs(b[f]).max()))
+        err[zi.FIELDS[f]] = {"rel_L2": (num2 / max(den2, 1e-300)) ** 0.5,
+                             "rel_Linf": numi / max(deni, 1e-300)}
+    out = {"workload": "bl512x32", "steps": steps, "dt": dt, "runs": res, "errors": err,
+           "H_L2_ratio": res["fp32"]["H_L2"] / res["fp64"]["H_L2"],
+           "H_L2_excised_ratio": res["fp32"]["H_L2_excised"] / res["fp64"]["H_L2_excised"]}
+    print(json.dumps(out))
+
+
+def learned(nvariants: int = 6, epochs: int = 40):
+    import torch
+    import paper_2409_10383_amd as z4c
+    import z4c_inputs as zi
+    p = zi.params_default(6)
+    rng = np.random.default_rng(7)
+
+    def snapshot(m1, m2, xp, seed, steps):
+        mesh = zi.uniform_mesh((16, 16, 16), 16, 4, (-16.0,) * 3, (16.0,) * 3, zi.BC_OUTFLOW)
+        data = zi.brill_lindquist(mesh, [(m1, (xp, 0.0, 0.0)), (m2, (-xp, 0.0, 0.0))])
+        data = zi.add_perturbation(mesh, data, seed=seed, amp=1e-6)
+        m2h = zi.coarse_2h_mesh(mesh)
+        ph, p2 = z4c.Pack(mesh, p), z4c.Pack(m2h, p)
+        ph.upload(z4c.REG_U, data)
+        F, Y, D, flags = [], [], [], []
+        done = 0
+        for s in steps:
+            ph.rk4_step(0.25 * mesh.dx0, s - done)
+            done = s
+            z4c.inject_2h(ph, p2)
+            ph.fill_ghosts()
+            p2.fill_ghosts()
+            Y.append(z4c.labels(ph, ph.rhs(), p2, p2.rhs()))
+            dev = torch.empty(mesh.nb * 16, dtype=torch.float64, device="cuda")
+            F.append(z4c.features(ph, device_out=dev))
+            D.append(dev.view(mesh.nb, 16))
+        return F, Y, D
+
+    train = [(rng.uniform(0.3, 0.7), rng.uniform(0.3, 0.7), rng.uniform(3.0, 7.0), 10 + i)
+             for i in range(nvariants)]
+    test = [(0.5, 0.5, 5.0, 20), (rng.uniform(0.3, 0.7), rng.uniform(0.3, 0.7), rng.uniform(3, 7), 21)]
+    Ftr, Ytr, Dtr = [], [], []
+    for v in train:
+        F, Y, D = snapshot(*v, steps=(0, 4))
+        Ftr += F; Ytr += Y; Dtr += D
+    net = z4c.Mlp(zi.mlp_init(1))
+    Dall = torch.cat(Dtr)
+    net.fit_stats(Dall)
+    X = net.normalize(Dall)
+    T = torch.tensor(np.concatenate(Ytr).astype(np.float32), device="cuda")
+    loss = net.train(X, T, epochs=epochs, lr=3e-3, batch=4096)
+    rows = []
+    for v in test:
+        F, Y, D = snapshot(*v, steps=(0,))
+        pred = net.forward(net.normalize(D[0])).cpu().numpy()
+        y, f = Y[0], F[0]
+        for K in (64, 256):
+            truth = set(np.argsort(-y)[:K])
+            rows.append({"setup": list(map(float, v)), "K": K,
+                         "learned_precision": len(truth & set(np.argsort(-pred)[:K])) / K,
+                         "dchi_max_precision": len(truth & set(np.argsort(-f[:, 0])[:K])) / K})
+    print(json.dumps({"workload": "bbh4096x16", "train_samples": int(T.numel()),
+                      "final_mse": loss, "test": rows}))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["precision", "learned"])
+    ap.add_argument("--steps", type=int, default=100)
+    a = ap.parse_args(argv)
+    if a.what == "precision":
+        precision(a.steps)
+    else:
+        learned()
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -252,6 +252,26 @@ def add_perturbation(mesh: Mesh, data: List[np.ndarray], seed: int, amp: float =
     return data
 
 
+# ---------------------------------------------- learned indicator weights
+
+MLP_SIZES = [("W1", (64, 16)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (1, 64)),
+             ("b3", (1,))]
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """Seeded initial weights of the 16-64-64-1 network, packed W1, b1, W2,
+    b2, W3, b3: He-uniform weights, zero biases, float32-representable."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for name, shp in MLP_SIZES:
+        if name.startswith("W"):
+            lim = np.sqrt(6.0 / shp[1])
+            parts.append(rng.uniform(-lim, lim, size=shp).reshape(-1))
+        else:
+            parts.append(np.zeros(int(np.prod(shp))))
+    return np.concatenate(parts).astype(np.float32).astype(np.float64)
+
+
 # ------------------------------------------------------ standard workloads
 
 def params_default(fd_order: int, eta: float = 2.0) -> dict:
