@@ -38,6 +38,13 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP32 and batched multi-level measurements")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into "
+                         "profiles/traffic_<workload>_<precision>.json and exit")
     return ap.parse_args()
 
 
@@ -63,8 +70,97 @@ def cpu_baseline(workload):
                       f"Brill-Lindquist) on one host core, {sec:.1f} s"}
 
 
+def _pmc_rows(d, counter):
+    """(kernel name, counter value in KiB) per dispatch from a rocprofv3 csv run."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r.get("Kernel_Name", ""), float(r["Counter_Value"])))
+    return rows
+
+
+def summarize_pmc(args):
+    """HBM bytes per stage-kernel launch from FETCH_SIZE and WRITE_SIZE,
+    each scaled by what the same counter reads for a 1 GiB device copy."""
+    out = {"workload": args.workload, "precision": args.precision, "kernel_source_hash": kernel_hash()}
+    total = 0.0
+    for d, ctr in zip(args.summarize_pmc, ("FETCH_SIZE", "WRITE_SIZE")):
+        rows = _pmc_rows(d, ctr)
+        stage = [v for k, v in rows if "k_stage" in k]
+        copy = [v for k, v in rows if ("copy" in k.lower() or "elementwise" in k.lower())
+                and v > 0.5 * 1024 * 1024]
+        if not stage or not copy:
+            raise SystemExit(f"no k_stage or copy dispatches with {ctr} in {d}")
+        factor = (1 << 30) / (max(copy) * 1024.0)
+        kib = sum(stage) / len(stage)
+        out[ctr] = {"stage_kib_per_dispatch": kib, "copy_kib": max(copy), "scale": factor,
+                    "bytes_per_launch": kib * 1024.0 * factor}
+        total += kib * 1024.0 * factor
+    out["bytes_per_launch"] = total
+    path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.precision}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+def copy_calibration():
+    import torch
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
+
+def extra_runs(z4c, zi, torch):
+    """Batched multi-level pack (512 blocks, 4 levels, 8th order, graph
+    replay, autotuned tiles) and FP32 storage on the default workload."""
+    out = {}
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        mesh, p, data, dt, _ = zi.workload("bbh512mixed")
+        pk = z4c.Pack(mesh, dict(p, graph=1))
+        pk.upload(z4c.REG_U, data)
+        chosen, times = pk.autotune(reps=2, stream=s)
+        pk.rk4_step(dt, 1, stream=s)
+        s.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        pk.rk4_step(dt, 5, stream=s)
+        e1.record(s)
+        s.synchronize()
+        ms = e0.elapsed_time(e1)
+        out["batched_bbh512mixed_fp64"] = {
+            "zcps": pk.zones * 5 / (ms * 1e-3), "zones": pk.zones, "blocks": int(mesh.nb),
+            "levels": int(mesh.level.max()) + 1, "fd_order": 8, "graph": True,
+            "tile_variant": chosen, "autotune_ms": [float(x) for x in times]}
+        del pk
+        torch.cuda.empty_cache()
+        mesh, p, data, dt, _ = zi.workload("bl64x32")
+        pk = z4c.Pack(mesh, p, z4c.FP32_MIXED)
+        pk.upload(z4c.REG_U, data)
+        pk.rk4_step(dt, 2, stream=s)
+        s.synchronize()
+        e0.record(s)
+        pk.rk4_step(dt, 10, stream=s)
+        e1.record(s)
+        s.synchronize()
+        ms = e0.elapsed_time(e1)
+        out["fp32_storage_bl64x32"] = {"zcps": pk.zones * 10 / (ms * 1e-3)}
+        del pk
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
+    if args.summarize_pmc:
+        summarize_pmc(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "halo-exchange design is described in DESIGN.md but not built.", file=sys.stderr)
@@ -96,7 +192,7 @@ def main():
     # dominant kernel: per-launch duration from events around each launch
     pack.profile(True)
     pack.profile_read(reset=True)
-    pack.rk4_step(dt, args.profile_steps)
+    pack.rk4_step(dt, max(args.profile_steps, 1))
     st_ms, st_n, fill_ms, fill_n, _, _ = pack.profile_read(reset=True)
     pack.profile(False)
     avg_stage_s = st_ms / st_n * 1e-3
@@ -134,6 +230,12 @@ def main():
                      "avg_launch_ms": st_ms / st_n, "launches": int(st_n),
                      "ghost_fill_avg_ms": (fill_ms / fill_n) if fill_n else None},
     }
+    if args.copy_calibration:
+        copy_calibration()
+    if not args.no_extras:
+        del pack
+        torch.cuda.empty_cache()
+        out["extras"] = extra_runs(z4c, zi, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

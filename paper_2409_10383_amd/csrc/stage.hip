@@ -121,15 +121,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     const int c = ((tz + R) * SY + (ty + R)) * SX + (tx + R);
     const int sxy = SX * SY;
 
-    // stage field f (tile + halo R) into LDS
+    // origin of the staged tile (tile + halo R) in the ghosted block
     const int64_t base0 = ((int64_t)(w.k0 - R + g) * E + (w.j0 - R + g)) * E + (w.i0 - R + g);
-    auto stage = [&](int f) {
-        const T* __restrict__ p = srcb + f * slab + base0;
-        for (int q = t; q < G::NS; q += 256) {
-            const int x = q % SX, y = (q / SX) % SY, z = q / sxy;
-            tile[q] = (C)p[((int64_t)z * E + y) * E + x];
-        }
-    };
     // d_x f on the y/z halo and d_y f on the z halo (for mixed derivatives)
     auto first_pass = [&]() {
         for (int q = t; q < G::NDX; q += 256) {
@@ -197,135 +190,132 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     using T1 = std::integral_constant<bool, true>;
     using F0 = std::integral_constant<bool, false>;
 
-    // ---- conformal metric: first derivatives, Ricci second-derivative term
-#pragma unroll 1
-    for (int p = 0; p < 6; ++p) {
-        __syncthreads();
-        stage(F_GXX + p);
-        __syncthreads();
-        first_pass();
-        __syncthreads();
-        C d1[3], d2[3], mxy, mxz, myz;
-        sweep(F_GXX + p, false, d1, d2, T1(), T1());
-        mixed(mxy, mxz, myz);
+    // ---- the 22 fields through LDS, in the order below; the global loads of
+    // the next field are issued before the current one is processed, so
+    // their latency overlaps the stencil work
+    constexpr int NPRE = (G::NS + 255) / 256;
+    T pre[NPRE];
+    auto fetch = [&](int f) {
+        const T* __restrict__ p = srcb + f * slab + base0;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            // store d_d g~_p (p is a runtime loop index: select)
+        for (int r = 0; r < NPRE; ++r) {
+            const int q = t + 256 * r;
+            if (q < G::NS) {
+                const int x = q % SX, y = (q / SX) % SY, z = q / sxy;
+                pre[r] = p[((int64_t)z * E + y) * E + x];
+            }
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int r = 0; r < NPRE; ++r) {
+            const int q = t + 256 * r;
+            if (q < G::NS) tile[q] = (C)pre[r];
+        }
+    };
+    // slot -> field: g~ (6), chi, alpha, beta (3), Gamma~ (3), Khat, Theta, A~ (6)
+    auto field_of = [](int sl) {
+        return sl < 6 ? F_GXX + sl : sl == 6 ? F_CHI : sl == 7 ? F_ALPHA : sl < 11 ? F_BETAX + (sl - 8)
+             : sl < 14 ? F_GAMX + (sl - 11) : sl == 14 ? F_KH : sl == 15 ? F_TH : F_AXX + (sl - 16);
+    };
+    fetch(field_of(0));
+#pragma unroll 1
+    for (int sl = 0; sl < NF; ++sl) {
+        __syncthreads();
+        put();
+        __syncthreads();
+        if (sl + 1 < NF) fetch(field_of(sl + 1));
+        if (sl < 6) {
+            // conformal metric: first derivatives, Ricci second-derivative term
+            const int p = sl;
+            first_pass();
+            __syncthreads();
+            C d1[3], d2[3], mxy, mxz, myz;
+            sweep(F_GXX + p, false, d1, d2, T1(), T1());
+            mixed(mxy, mxz, myz);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+#pragma unroll
+                for (int pp = 0; pp < 6; ++pp)
+                    if (pp == p) dg[d][pp] = d1[d];
+            }
+            const C r = -(C)0.5 * (gu[0] * d2[0] + gu[3] * d2[1] + gu[5] * d2[2] +
+                                   (C)2 * ih2 * (gu[1] * mxy + gu[2] * mxz + gu[4] * myz));
 #pragma unroll
             for (int pp = 0; pp < 6; ++pp)
-                if (pp == p) dg[d][pp] = d1[d];
-        }
-        const C r = -(C)0.5 * (gu[0] * d2[0] + gu[3] * d2[1] + gu[5] * d2[2] +
-                               (C)2 * ih2 * (gu[1] * mxy + gu[2] * mxz + gu[4] * myz));
+                if (pp == p) Rt[pp] = r;
+        } else if (sl < 8) {
+            // chi and alpha: first and second derivatives
+            first_pass();
+            __syncthreads();
+            C d1[3], d2[3], mxy, mxz, myz;
+            const bool is_chi = sl == 6;
+            sweep(is_chi ? F_CHI : F_ALPHA, !is_chi, d1, d2, T1(), T1());
+            mixed(mxy, mxz, myz);
+            C* dd = is_chi ? ddchi : ddal;
+            C* d = is_chi ? dchi : dal;
+            d[0] = d1[0]; d[1] = d1[1]; d[2] = d1[2];
+            dd[0] = d2[0]; dd[3] = d2[1]; dd[5] = d2[2];
+            dd[1] = mxy * ih2; dd[2] = mxz * ih2; dd[4] = myz * ih2;
+        } else if (sl < 11) {
+            // shift: first derivatives, g~^jk d_j d_k beta^i and d_j d_k beta^k
+            const int q = sl - 8;
+            first_pass();
+            __syncthreads();
+            C d1[3], d2[3], mxy, mxz, myz;
+            sweep(F_BETAX + q, true, d1, d2, T1(), T1());
+            mixed(mxy, mxz, myz);
+            mxy *= ih2; mxz *= ih2; myz *= ih2;
+            const C dd[6] = {d2[0], mxy, mxz, d2[1], myz, d2[2]};
+            const C lb = gu[0] * dd[0] + gu[3] * dd[3] + gu[5] * dd[5] +
+                         (C)2 * (gu[1] * dd[1] + gu[2] * dd[2] + gu[4] * dd[4]);
 #pragma unroll
-        for (int pp = 0; pp < 6; ++pp)
-            if (pp == p) Rt[pp] = r;
-    }
-    // ---- chi and alpha: first and second derivatives
-    {
-        __syncthreads();
-        stage(F_CHI);
-        __syncthreads();
-        first_pass();
-        __syncthreads();
-        C d2[3], mxy, mxz, myz;
-        sweep(F_CHI, false, dchi, d2, T1(), T1());
-        mixed(mxy, mxz, myz);
-        ddchi[0] = d2[0]; ddchi[3] = d2[1]; ddchi[5] = d2[2];
-        ddchi[1] = mxy * ih2; ddchi[2] = mxz * ih2; ddchi[4] = myz * ih2;
-    }
-    {
-        __syncthreads();
-        stage(F_ALPHA);
-        __syncthreads();
-        first_pass();
-        __syncthreads();
-        C d2[3], mxy, mxz, myz;
-        sweep(F_ALPHA, true, dal, d2, T1(), T1());
-        mixed(mxy, mxz, myz);
-        ddal[0] = d2[0]; ddal[3] = d2[1]; ddal[5] = d2[2];
-        ddal[1] = mxy * ih2; ddal[2] = mxz * ih2; ddal[4] = myz * ih2;
-    }
-    // ---- shift: first derivatives, g~^jk d_j d_k beta^i and d_j d_k beta^k
-#pragma unroll 1
-    for (int q = 0; q < 3; ++q) {
-        __syncthreads();
-        stage(F_BETAX + q);
-        __syncthreads();
-        first_pass();
-        __syncthreads();
-        C d1[3], d2[3], mxy, mxz, myz;
-        sweep(F_BETAX + q, true, d1, d2, T1(), T1());
-        mixed(mxy, mxz, myz);
-        mxy *= ih2; mxz *= ih2; myz *= ih2;
-        const C dd[6] = {d2[0], mxy, mxz, d2[1], myz, d2[2]};
-        const C lb = gu[0] * dd[0] + gu[3] * dd[3] + gu[5] * dd[5] +
-                     (C)2 * (gu[1] * dd[1] + gu[2] * dd[2] + gu[4] * dd[4]);
+            for (int qq = 0; qq < 3; ++qq)
+                if (qq == q) {
+                    Lb[qq] = lb;
 #pragma unroll
-        for (int qq = 0; qq < 3; ++qq)
-            if (qq == q) {
-                Lb[qq] = lb;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) dbe[d][qq] = d1[d];
-                // B_j += d_j d_q beta^q
-                Bj[0] += dd[S(0, qq)];
-                Bj[1] += dd[S(1, qq)];
-                Bj[2] += dd[S(2, qq)];
-            }
-    }
-    // ---- Gamma~: its first derivatives enter R~_ij only
-#pragma unroll 1
-    for (int q = 0; q < 3; ++q) {
-        __syncthreads();
-        stage(F_GAMX + q);
-        __syncthreads();
-        C d1[3], d2[3];
-        sweep(F_GAMX + q, false, d1, d2, T1(), F0());
-        // R~_ij += 1/2 (g~_qi d_j G^q + g~_qj d_i G^q)
-#pragma unroll
-        for (int qq = 0; qq < 3; ++qq)
-            if (qq == q) {
-#pragma unroll
-                for (int pp = 0; pp < 6; ++pp) {
-                    const int ii = SA(pp), jj = SB(pp);
-                    Rt[pp] += (C)0.5 * (gdn[S(qq, ii)] * d1[jj] + gdn[S(qq, jj)] * d1[ii]);
+                    for (int d = 0; d < 3; ++d) dbe[d][qq] = d1[d];
+                    // B_j += d_j d_q beta^q
+                    Bj[0] += dd[S(0, qq)];
+                    Bj[1] += dd[S(1, qq)];
+                    Bj[2] += dd[S(2, qq)];
                 }
+        } else if (sl < 14) {
+            // Gamma~: its first derivatives enter R~_ij only
+            const int q = sl - 11;
+            C d1[3], d2[3];
+            sweep(F_GAMX + q, false, d1, d2, T1(), F0());
+            // R~_ij += 1/2 (g~_qi d_j G^q + g~_qj d_i G^q)
+#pragma unroll
+            for (int qq = 0; qq < 3; ++qq)
+                if (qq == q) {
+#pragma unroll
+                    for (int pp = 0; pp < 6; ++pp) {
+                        const int ii = SA(pp), jj = SB(pp);
+                        Rt[pp] += (C)0.5 * (gdn[S(qq, ii)] * d1[jj] + gdn[S(qq, jj)] * d1[ii]);
+                    }
+                }
+        } else if (sl < 16) {
+            // Khat and Theta: 2 d Khat + d Theta
+            C d1[3], d2[3];
+            sweep(sl == 14 ? F_KH : F_TH, false, d1, d2, T1(), F0());
+            if (sl == 14) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) eK[d] = (C)2 * d1[d];
+            } else {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) eK[d] += d1[d];
             }
-    }
-    // ---- Khat and Theta: 2 d Khat + d Theta
-    {
-        __syncthreads();
-        stage(F_KH);
-        __syncthreads();
-        C d1[3], d2[3];
-        sweep(F_KH, false, d1, d2, T1(), F0());
-#pragma unroll
-        for (int d = 0; d < 3; ++d) eK[d] = (C)2 * d1[d];
-        __syncthreads();
-        stage(F_TH);
-        __syncthreads();
-        sweep(F_TH, false, d1, d2, T1(), F0());
-#pragma unroll
-        for (int d = 0; d < 3; ++d) eK[d] += d1[d];
-    }
-    // ---- A~_ij: advection and dissipation only
-#pragma unroll 1
-    for (int p = 0; p < 6; ++p) {
-        __syncthreads();
-        stage(F_AXX + p);
-        __syncthreads();
-        C d1[3], d2[3], ad;
-        {
-            const bool a_on = adv;
-            ad = 0;
+        } else {
+            // A~_ij: advection and dissipation only
+            C ad = 0;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 C x1, x2;
-                axis_pass<N, C, false, false>(tile, c, st3[d], a_on ? be[d] : (C)0, sig, x1, x2, ad);
+                axis_pass<N, C, false, false>(tile, c, st3[d], adv ? be[d] : (C)0, sig, x1, x2, ad);
             }
+            put_adk(F_AXX + (sl - 16), ad * ih);
         }
-        (void)d1; (void)d2;
-        put_adk(F_AXX + p, ad * ih);
     }
 
     // ---- centre values and the per-zone algebra
