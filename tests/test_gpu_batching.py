@@ -61,9 +61,10 @@ def test_graph_replay_matches_eager():
             s.synchronize()
             eager.rk4_step(dt, 1, stream=s)       # eager work between replays
             s.synchronize()
-            a = graph.state_view(z().REG_U).cpu()
-            b = eager.state_view(z().REG_U).cpu()
-            assert torch.equal(a, b), f"replay {step}"
+            a = graph.state_view(z().REG_U).cpu().numpy()
+            b = eager.state_view(z().REG_U).cpu().numpy()
+            # slab padding stays NaN in both: NaN-aware bitwise comparison
+            assert np.array_equal(a, b, equal_nan=True), f"replay {step}"
 
 
 def test_autotune_selects_fastest_valid():

@@ -95,5 +95,16 @@ def test_bbh512mixed_full_size():
             cand = np.where((mesh.level == lev) & (mesh.n == n))[0]
             if cand.size:
                 sample += list(rng.choice(cand, size=min(3, cand.size), replace=False))
+    # include the blocks holding the punctures, where the RHS is largest
+    for xp in (5.0, -5.0):
+        for b in range(mesh.nb):
+            hb = mesh.dx(b)
+            x0 = [mesh.lo[a] + mesh.ilo[b, a] * hb for a in range(3)]
+            if all(x0[a] <= (xp, 0.0, 0.0)[a] <= x0[a] + mesh.n[b] * hb for a in range(3)):
+                sample.append(b)
+    sample = sorted(set(int(b) for b in sample))
     ro = oracle.rhs(om, p, u, fill=False, blocks=sample)
-    assert_parity([rg[b] for b in sample], [ro[b] for b in sample], what="rhs bbh512mixed sample")
+    S = max(np.abs(data[b][[0, 1, 4, 6, 18]]).max() for b in sample)
+    hmin = mesh.dx(int(mesh.level.max()))
+    assert_parity([rg[b] for b in sample], [ro[b] for b in sample], what="rhs bbh512mixed sample",
+                  mode="rounding", S=S, order=8, h=hmin)
