@@ -123,18 +123,29 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
 
     // origin of the staged tile (tile + halo R) in the ghosted block
     const int64_t base0 = ((int64_t)(w.k0 - R + g) * E + (w.j0 - R + g)) * E + (w.i0 - R + g);
-    // d_x f on the y/z halo and d_y f on the z halo (for mixed derivatives)
+    // d_x f on the y/z halo and d_y f on the z halo (for mixed derivatives);
+    // the staged-tile index of each of this thread's points is fixed per tile
+    constexpr int NQX = (G::NDX + 255) / 256, NQY = (G::NDY + 255) / 256;
+    int ccx[NQX], ccy[NQY];
+#pragma unroll
+    for (int r = 0; r < NQX; ++r) {
+        const int q = t + 256 * r;
+        const int x = q % TX, y = (q / TX) % G::DXY, z = q / (TX * G::DXY);
+        ccx[r] = ((z + R - N) * SY + (y + R - N)) * SX + (x + R);
+    }
+#pragma unroll
+    for (int r = 0; r < NQY; ++r) {
+        const int q = t + 256 * r;
+        const int x = q % TX, y = (q / TX) % TY, z = q / (TX * TY);
+        ccy[r] = ((z + R - N) * SY + (y + R)) * SX + (x + R);
+    }
     auto first_pass = [&]() {
-        for (int q = t; q < G::NDX; q += 256) {
-            const int x = q % TX, y = (q / TX) % G::DXY, z = q / (TX * G::DXY);
-            const int cc = ((z + R - N) * SY + (y + R - N)) * SX + (x + R);
-            dxs[q] = fd1<N, C>(tile + cc, 1);
-        }
-        for (int q = t; q < G::NDY; q += 256) {
-            const int x = q % TX, y = (q / TX) % TY, z = q / (TX * TY);
-            const int cc = ((z + R - N) * SY + (y + R)) * SX + (x + R);
-            dys[q] = fd1<N, C>(tile + cc, SX);
-        }
+#pragma unroll
+        for (int r = 0; r < NQX; ++r)
+            if (t + 256 * r < G::NDX) dxs[t + 256 * r] = fd1<N, C>(tile + ccx[r], 1);
+#pragma unroll
+        for (int r = 0; r < NQY; ++r)
+            if (t + 256 * r < G::NDY) dys[t + 256 * r] = fd1<N, C>(tile + ccy[r], SX);
     };
     // mixed derivatives of the staged field at this zone: xy, xz, yz
     auto mixed = [&](C& mxy, C& mxz, C& myz) {
@@ -195,16 +206,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     // their latency overlaps the stencil work
     constexpr int NPRE = (G::NS + 255) / 256;
     T pre[NPRE];
+    int soff[NPRE];  // offsets of this thread's staged cells from the tile origin
+#pragma unroll
+    for (int r = 0; r < NPRE; ++r) {
+        const int q = t + 256 * r;
+        const int x = q % SX, y = (q / SX) % SY, z = q / sxy;
+        soff[r] = (z * E + y) * E + x;
+    }
     auto fetch = [&](int f) {
         const T* __restrict__ p = srcb + f * slab + base0;
 #pragma unroll
-        for (int r = 0; r < NPRE; ++r) {
-            const int q = t + 256 * r;
-            if (q < G::NS) {
-                const int x = q % SX, y = (q / SX) % SY, z = q / sxy;
-                pre[r] = p[((int64_t)z * E + y) * E + x];
-            }
-        }
+        for (int r = 0; r < NPRE; ++r)
+            if (t + 256 * r < G::NS) pre[r] = p[soff[r]];
     };
     auto put = [&]() {
 #pragma unroll

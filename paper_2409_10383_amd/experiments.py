@@ -65,10 +65,14 @@ def learned(nvariants: int = 6, epochs: int = 40):
     p = zi.params_default(6)
     rng = np.random.default_rng(7)
 
-    def snapshot(m1, m2, xp, seed, steps):
-        mesh = zi.uniform_mesh((16, 16, 16), 16, 4, (-16.0,) * 3, (16.0,) * 3, zi.BC_OUTFLOW)
-        data = zi.brill_lindquist(mesh, [(m1, (xp, 0.0, 0.0)), (m2, (-xp, 0.0, 0.0))])
-        data = zi.add_perturbation(mesh, data, seed=seed, amp=1e-6)
+    mesh = zi.uniform_mesh((16, 16, 16), 16, 4, (-16.0,) * 3, (16.0,) * 3, zi.BC_OUTFLOW)
+
+    def snapshot(m1, m2, xp, yp, steps):
+        """Two BL punctures (masses m1, m2) at (xp, yp, 0) and (-xp, -yp, 0);
+        features and labels at the listed RK4 step counts."""
+        print(f"snapshot m=({m1:.2f},{m2:.2f}) x=({xp:.2f},{yp:.2f}) steps={steps}", file=sys.stderr,
+              flush=True)
+        data = zi.brill_lindquist(mesh, [(m1, (xp, yp, 0.0)), (m2, (-xp, -yp, 0.0))])
         m2h = zi.coarse_2h_mesh(mesh)
         ph, p2 = z4c.Pack(mesh, p), z4c.Pack(m2h, p)
         ph.upload(z4c.REG_U, data)
@@ -86,19 +90,23 @@ def learned(nvariants: int = 6, epochs: int = 40):
             D.append(dev.view(mesh.nb, 16))
         return F, Y, D
 
-    train = [(rng.uniform(0.3, 0.7), rng.uniform(0.3, 0.7), rng.uniform(3.0, 7.0), 10 + i)
-             for i in range(nvariants)]
-    test = [(0.5, 0.5, 5.0, 20), (rng.uniform(0.3, 0.7), rng.uniform(0.3, 0.7), rng.uniform(3, 7), 21)]
+    def setup():
+        return (rng.uniform(0.3, 0.7), rng.uniform(0.3, 0.7), rng.uniform(3.0, 7.0),
+                rng.uniform(-1.0, 1.0))
+    train = [setup() for _ in range(nvariants)]
+    test = [(0.5, 0.5, 5.0, 0.0), setup()]
     Ftr, Ytr, Dtr = [], [], []
     for v in train:
-        F, Y, D = snapshot(*v, steps=(0, 4))
+        F, Y, D = snapshot(*v, steps=(0, 8))
         Ftr += F; Ytr += Y; Dtr += D
     net = z4c.Mlp(zi.mlp_init(1))
     Dall = torch.cat(Dtr)
     net.fit_stats(Dall)
     X = net.normalize(Dall)
     T = torch.tensor(np.concatenate(Ytr).astype(np.float32), device="cuda")
+    print(f"training on {T.numel()} blocks", file=sys.stderr, flush=True)
     loss = net.train(X, T, epochs=epochs, lr=3e-3, batch=4096)
+    print(f"final training MSE {loss:.4f}", file=sys.stderr, flush=True)
     rows = []
     for v in test:
         F, Y, D = snapshot(*v, steps=(0,))
