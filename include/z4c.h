@@ -120,6 +120,8 @@ typedef struct {
     int64_t zones;              /* active cells of the pack                   */
     int32_t state_elem_bytes;   /* 8 (FP64) or 4 (FP32_MIXED)                 */
     int32_t nwork;              /* work items of the fused stage kernel       */
+    int64_t nxfer;              /* cross-level copies/restrictions per fill   */
+    int64_t nprolong;           /* cross-level prolongated ghost cells        */
 } z4c_layout;
 
 /* Norm region for z4c_constraints: zones with centre within r_exc of any

@@ -49,7 +49,7 @@ class Params(C.Structure):
 class Layout(C.Structure):
     _fields_ = [("reg_bytes", C.c_size_t * 4), ("workspace_bytes", C.c_size_t),
                 ("nblocks", C.c_int64), ("zones", C.c_int64), ("state_elem_bytes", C.c_int32),
-                ("nwork", C.c_int32)]
+                ("nwork", C.c_int32), ("nxfer", C.c_int64), ("nprolong", C.c_int64)]
 
 
 class NormRegion(C.Structure):

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <type_traits>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -30,9 +31,10 @@ struct z4c_pack {
     // cross-level fill tables
     std::vector<XferItem> xfer;
     std::vector<ProlongItem> prol;
+    std::vector<ProlongGroup> pgrp;
     std::vector<double> rw, pw, wtab;
     int64_t shadow_elems = 0;
-    size_t ws_xfer = 0, ws_prol = 0, ws_w = 0, ws_shadow = 0;
+    size_t ws_xfer = 0, ws_prol = 0, ws_pgrp = 0, ws_w = 0, ws_shadow = 0;
     size_t ws_first = 0, ws_feat = 0, ws_x = 0, ws_y = 0;
     std::vector<int32_t> first_work;
     int maxghost = 0;
@@ -195,6 +197,14 @@ struct Geo {
     }
 };
 
+// Non-persistent stage grid: the XCD-aware slot -> tile map interleaves
+// 8 slices of ceil(nwork/8) tiles, so it needs 8 * ceil(nwork/8) slots
+// (slots past the end map to tile indices >= nwork and exit).
+static int stage_grid(size_t nwork)
+{
+    return (int)(8 * ((nwork + 7) / 8));
+}
+
 // Build the transfer / prolongation lists of a multi-level pack.
 int build_xlevel(z4c_pack* pk)
 {
@@ -223,6 +233,7 @@ int build_xlevel(z4c_pack* pk)
         for (int a = 0; a < 3; ++a) S0[a] = fdiv(B.ilo[a] - g, 2) - (np + 1);
         int64_t shoff = -1;
         std::vector<uint8_t> mark;
+        std::unordered_map<int64_t, size_t> pgmap;  // parent's child-(0,0,0) cell -> group
         for (int k = 0; k < E; ++k)
             for (int j = 0; j < E; ++j)
                 for (int i = 0; i < E; ++i) {
@@ -248,6 +259,7 @@ int build_xlevel(z4c_pack* pk)
                     if (geo.leaf(l - 1, P) < 0) return Z4C_EINVAL;
                     // prolongation: stencil around the periodic-unwrapped or clamped index
                     const int64_t* Iu = (pk->p.bc == Z4C_BC_PERIODIC) ? G : Gb;
+                    const bool regular = (Iu[0] == G[0] && Iu[1] == G[1] && Iu[2] == G[2]);
                     int64_t s[3];
                     int parity = 0;
                     for (int a = 0; a < 3; ++a) {
@@ -257,6 +269,14 @@ int build_xlevel(z4c_pack* pk)
                         s[a] = (np % 2) ? J - (np - 1) / 2 : (odd ? J - np / 2 + 1 : J - np / 2);
                         if (s[a] < S0[a] || s[a] + np > S0[a] + SE) return Z4C_EINVAL;
                     }
+                    if (regular) {
+                        // grouped by coarse parent: union stencil starts one cell lower
+                        // for even np (parity-0 window)
+                        for (int a = 0; a < 3; ++a)
+                            if (np % 2 == 0 && (parity >> a & 1)) s[a] -= 1;
+                        for (int a = 0; a < 3; ++a)
+                            if (s[a] < S0[a] || s[a] + np + (np % 2 == 0) > S0[a] + SE) return Z4C_EINVAL;
+                    }
                     if (shoff < 0) {
                         shoff = pk->shadow_elems;
                         const int64_t cells = SE * SE * SE;
@@ -264,9 +284,10 @@ int build_xlevel(z4c_pack* pk)
                         mark.assign((size_t)(SE * SE * SE), 0);
                     }
                     const int64_t fstride = (SE * SE * SE + per256 - 1) / per256 * per256;
-                    for (int kz = 0; kz < np; ++kz)
-                        for (int jy = 0; jy < np; ++jy)
-                            for (int ix = 0; ix < np; ++ix) {
+                    const int nu = regular ? np + (np % 2 == 0) : np;
+                    for (int kz = 0; kz < nu; ++kz)
+                        for (int jy = 0; jy < nu; ++jy)
+                            for (int ix = 0; ix < nu; ++ix) {
                                 const int64_t K[3] = {s[0] + ix, s[1] + jy, s[2] + kz};
                                 const int64_t loc = ((K[2] - S0[2]) * SE + (K[1] - S0[1])) * SE + (K[0] - S0[0]);
                                 if (mark[loc]) continue;
@@ -292,14 +313,36 @@ int build_xlevel(z4c_pack* pk)
                                 }
                                 pk->xfer.push_back(it);
                             }
-                    ProlongItem pi;
-                    pi.dst = dcell;
-                    pi.sh = shoff + ((s[2] - S0[2]) * SE + (s[1] - S0[1])) * SE + (s[0] - S0[0]);
-                    pi.block = b;
-                    pi.se = (int32_t)SE;
-                    pi.parity = parity;
-                    pi.pad = (int32_t)fstride;  // field stride of the shadow box
-                    pk->prol.push_back(pi);
+                    const int64_t shs = shoff + ((s[2] - S0[2]) * SE + (s[1] - S0[1])) * SE + (s[0] - S0[0]);
+                    if (regular) {
+                        // child (cx, cy, cz) of the parent; the (0,0,0) child's cell
+                        const int cx = parity & 1, cy = (parity >> 1) & 1, cz = (parity >> 2) & 1;
+                        const int64_t d0 = D.off + ((int64_t)(k - cz) * E + (j - cy)) * E + (i - cx);
+                        // key: child (0,0,0) index shifted by one (it can sit at -1)
+                        const int64_t key = ((int64_t)(k - cz + 1) * (E + 2) + (j - cy + 1)) * (E + 2) + (i - cx + 1);
+                        auto itg = pgmap.find(key);
+                        if (itg == pgmap.end()) {
+                            ProlongGroup pg;
+                            pg.dst = d0;
+                            pg.sh = shs;
+                            pg.block = b;
+                            pg.se = (int32_t)SE;
+                            pg.mask = 0;
+                            pg.fstride = (int32_t)fstride;
+                            itg = pgmap.emplace(key, pk->pgrp.size()).first;
+                            pk->pgrp.push_back(pg);
+                        }
+                        pk->pgrp[itg->second].mask |= 1 << (cz * 4 + cy * 2 + cx);
+                    } else {
+                        ProlongItem pi;
+                        pi.dst = dcell;
+                        pi.sh = shs;
+                        pi.block = b;
+                        pi.se = (int32_t)SE;
+                        pi.parity = parity;
+                        pi.pad = (int32_t)fstride;  // field stride of the shadow box
+                        pk->prol.push_back(pi);
+                    }
                 }
     }
     return Z4C_OK;
@@ -479,6 +522,7 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
     pk->ws_y = o;      o = align256(o + sizeof(float) * nblocks);
     pk->ws_xfer = o;   o = align256(o + sizeof(XferItem) * pk->xfer.size());
     pk->ws_prol = o;   o = align256(o + sizeof(ProlongItem) * pk->prol.size());
+    pk->ws_pgrp = o;   o = align256(o + sizeof(ProlongGroup) * pk->pgrp.size());
     pk->ws_w = o;      o = align256(o + sizeof(double) * 80);
     pk->ws_shadow = o; o = align256(o + esz * (size_t)pk->shadow_elems);
     pk->ws_total = o;
@@ -500,6 +544,8 @@ int z4c_pack_query(const z4c_pack* pk, z4c_layout* out)
     out->zones = pk->zones;
     out->state_elem_bytes = pk->p.precision == Z4C_FP64 ? 8 : 4;
     out->nwork = (int32_t)pk->work.size();
+    out->nxfer = (int64_t)pk->xfer.size();
+    out->nprolong = (int64_t)pk->prol.size() + 8 * (int64_t)pk->pgrp.size();
     return Z4C_OK;
 }
 
@@ -540,6 +586,9 @@ int z4c_pack_bind(z4c_pack* pk, void* const regs[Z4C_NREG], void* workspace, siz
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !pk->prol.empty())
         e = hipMemcpyAsync(ws + pk->ws_prol, pk->prol.data(), sizeof(ProlongItem) * pk->prol.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !pk->pgrp.empty())
+        e = hipMemcpyAsync(ws + pk->ws_pgrp, pk->pgrp.data(), sizeof(ProlongGroup) * pk->pgrp.size(),
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess && pk->multilevel) {
         double wt[80];
@@ -625,6 +674,8 @@ int z4c_fill_ghosts(z4c_pack* pk, int32_t reg, void* stream)
         x.pw = x.rw + 64;
         x.nxfer = (int64_t)pk->xfer.size();
         x.nprol = (int64_t)pk->prol.size();
+        x.pgrp = reinterpret_cast<const ProlongGroup*>(pk->ws + pk->ws_pgrp);
+        x.npgrp = (int64_t)pk->pgrp.size();
         x.npts = pk->p.nghost + 1;
         e = launch_xlevel(pk->p.precision, x, as_stream(stream));
     }
@@ -657,7 +708,7 @@ int z4c_rhs(z4c_pack* pk, int32_t src_reg, void* rhs_out, void* stream)
     a.src = pk->reg[src_reg];
     a.rhs_out = static_cast<double*>(rhs_out);
     a.stage = 0;
-    const int grid = pk->persistent ? pk->grid_persistent : (int)pk->work.size();
+    const int grid = pk->persistent ? pk->grid_persistent : stage_grid(pk->work.size());
     hipError_t e = launch_stage(pk->p.fd_order / 2, pk->p.precision, pk->variant, a, grid, as_stream(stream));
     if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "rhs launch: %s", hipGetErrorString(e));
     return Z4C_OK;
@@ -679,7 +730,7 @@ int z4c_rk4_stage(z4c_pack* pk, int32_t stage, double dt, void* stream)
     a.dt = dt;
     a.stage = stage;
     ProfScope ps(pk, as_stream(stream), 0);
-    const int grid = pk->persistent ? pk->grid_persistent : (int)pk->work.size();
+    const int grid = pk->persistent ? pk->grid_persistent : stage_grid(pk->work.size());
     hipError_t e = launch_stage(pk->p.fd_order / 2, pk->p.precision, pk->variant, a, grid, as_stream(stream));
     if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "stage launch: %s", hipGetErrorString(e));
     return Z4C_OK;

@@ -147,15 +147,65 @@ __global__ __launch_bounds__(256) void k_prolong(const XlevelArgs a)
     }
 }
 
+// grouped prolongation: one coarse parent, up to 8 fine children, separable
+// (x, then y, then z) over the union stencil
+template <class T>
+__global__ __launch_bounds__(256) void k_prolong_group(const XlevelArgs a)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.npgrp) return;
+    const ProlongGroup it = a.pgrp[q];
+    const BlockDev B = a.blocks[it.block];
+    const T* __restrict__ sh = (const T*)a.shadow + it.sh;
+    T* dst = (T*)a.reg + it.dst;
+    const int np = a.npts;
+    const int even = (np % 2 == 0);
+    const int nu = np + even;          // union stencil points per axis
+    const int64_t se = it.se, E = B.E;
+    const double* w0 = a.pw;           // parity 0 weights, union points 0..np-1
+    const double* w1 = a.pw + 8;       // parity 1 weights, union points even..even+np-1
+    for (int f = 0; f < NF; ++f) {
+        const T* p = sh + (int64_t)f * it.fstride;
+        double acc[2][2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
+        for (int kz = 0; kz < nu; ++kz) {
+            double ay[2][2] = {{0, 0}, {0, 0}};
+            for (int jy = 0; jy < nu; ++jy) {
+                const T* row = p + (kz * se + jy) * se;
+                double ax0 = 0.0, ax1 = 0.0;
+                for (int ix = 0; ix < nu; ++ix) {
+                    const double v = (double)row[ix];
+                    if (ix < np) ax0 += w0[ix] * v;
+                    if (ix >= even) ax1 += w1[ix - even] * v;
+                }
+                if (jy < np) { ay[0][0] += w0[jy] * ax0; ay[0][1] += w0[jy] * ax1; }
+                if (jy >= even) { ay[1][0] += w1[jy - even] * ax0; ay[1][1] += w1[jy - even] * ax1; }
+            }
+            for (int cy = 0; cy < 2; ++cy)
+                for (int cx = 0; cx < 2; ++cx) {
+                    if (kz < np) acc[0][cy][cx] += w0[kz] * ay[cy][cx];
+                    if (kz >= even) acc[1][cy][cx] += w1[kz - even] * ay[cy][cx];
+                }
+        }
+        for (int cz = 0; cz < 2; ++cz)
+            for (int cy = 0; cy < 2; ++cy)
+                for (int cx = 0; cx < 2; ++cx)
+                    if (it.mask & (1 << (cz * 4 + cy * 2 + cx)))
+                        dst[(cz * E + cy) * E + cx + (int64_t)f * B.slab] = (T)acc[cz][cy][cx];
+    }
+}
+
 hipError_t launch_xlevel(int prec, const XlevelArgs& a, hipStream_t s)
 {
     const unsigned gx = (unsigned)((a.nxfer + 255) / 256), gp = (unsigned)((a.nprol + 255) / 256);
+    const unsigned gg = (unsigned)((a.npgrp + 255) / 256);
     if (prec == 0) {
         if (gx) hipLaunchKernelGGL(k_xfer<double>, dim3(gx), dim3(256), 0, s, a);
         if (gp) hipLaunchKernelGGL(k_prolong<double>, dim3(gp), dim3(256), 0, s, a);
+        if (gg) hipLaunchKernelGGL(k_prolong_group<double>, dim3(gg), dim3(256), 0, s, a);
     } else {
         if (gx) hipLaunchKernelGGL(k_xfer<float>, dim3(gx), dim3(256), 0, s, a);
         if (gp) hipLaunchKernelGGL(k_prolong<float>, dim3(gp), dim3(256), 0, s, a);
+        if (gg) hipLaunchKernelGGL(k_prolong_group<float>, dim3(gg), dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }

@@ -40,9 +40,10 @@ struct XlevelArgs {
     const BlockDev* blocks;
     const XferItem* xfer;
     const ProlongItem* prol;
+    const ProlongGroup* pgrp;
     const double* rw;         // restriction weights [8][8]: set d, point q
     const double* pw;         // prolongation weights [2][8]: parity, point q
-    int64_t nxfer, nprol;
+    int64_t nxfer, nprol, npgrp;
     int32_t npts;             // g + 1
 };
 

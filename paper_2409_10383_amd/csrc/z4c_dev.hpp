@@ -66,6 +66,18 @@ struct ProlongItem {
     int32_t pad;          // field stride of the shadow box (elements)
 };
 
+// Prolongation of the (up to) 8 fine ghost children of one coarse parent:
+// they share the union of their stencils, (g+2)^3 coarse values for even
+// g+1 (the two parities' windows differ by one cell), (g+1)^3 for odd.
+struct ProlongGroup {
+    int64_t dst;          // register element offset of child (0,0,0), field 0
+    int64_t sh;           // shadow element offset of the union stencil origin
+    int32_t block;        // destination block (field stride, row length)
+    int32_t se;           // shadow box extent per axis
+    int32_t mask;         // bit (cz*4 + cy*2 + cx): child is a ghost to fill
+    int32_t fstride;      // field stride of the shadow box (elements)
+};
+
 // physics / method parameters as the kernels read them
 struct ParamsDev {
     double ko_sigma, kappa1, kappa2, eta, mu_S, chi_floor, alpha_floor;

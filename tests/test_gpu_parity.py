@@ -161,3 +161,34 @@ def test_bl64x32_full_size_rhs_parity():
     mesh, p, data, dt, _ = zi.workload("bl64x32")
     _, rg = gpu_rhs(mesh, p, data)
     assert_parity(rg, ora_rhs(mesh, p, data), what="rhs bl64x32")
+
+
+# tile counts that are not a multiple of 8 (the XCD-interleaved slot map has
+# a short last slice): one 24^3 block = 54 tiles, 3x3x1 blocks of 8^3 = 18
+RAGGED = {"one24": ((1, 1, 1), 24, (6.0, 6.0, 6.0)), "three_by_three8": ((3, 3, 1), 8, (6.0, 6.0, 2.0))}
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("shape", sorted(RAGGED))
+def test_ragged_tile_count_parity(shape, persistent):
+    nblk, n, half = RAGGED[shape]
+    mesh = zi.uniform_mesh(nblk, n, 4, tuple(-x for x in half), half, zi.BC_OUTFLOW)
+    data = zi.brill_lindquist(mesh, [(1.0, (0.0, 0.0, 0.0))])
+    data = zi.add_perturbation(mesh, data, seed=5, amp=1e-4)
+    p = zi.params_default(6)
+    pk = z().Pack(mesh, p)
+    assert pk.nwork % 8 != 0 and pk.nwork > 8
+    pk.set_variant(0, persistent)
+    pk.upload(z().REG_U, data)
+    pk.fill_ghosts(z().REG_U)
+    rg = pk.split_interior(pk.rhs(z().REG_U))
+    torch.cuda.synchronize()
+    assert_parity(rg, ora_rhs(mesh, p, data), what=f"rhs {shape}")
+    dt = 0.25 * mesh.dx0
+    pk.upload(z().REG_U, data)
+    pk.rk4_step(dt, 1)
+    om = oracle.OracleMesh(mesh)
+    regs = oracle.Registers(om, data)
+    oracle.rk4_steps(regs, p, dt, 1)
+    torch.cuda.synchronize()
+    assert_parity(pk.download(0), om.interiors(regs.U), what=f"step {shape}", mode="state")

@@ -192,6 +192,35 @@ def linear_wave(A: float = 1e-8, d: float = 1.0):
     return fn
 
 
+def linear_wave_diagonal(A: float = 1e-8, L: float = 1.0):
+    """Linearised TT wave travelling along the diagonal of a periodic cube
+    of side L (one wavelength across the cube in each direction):
+    h_ab = A e_ab sin(k.x - w t), k = (2 pi / L)(1, 1, 1), w = |k|,
+    e = u u - v v with u, v orthonormal and orthogonal to k; alpha = 1,
+    beta = 0, K_ab = -d_t h_ab / 2.  Period 2 pi / w = L / sqrt(3)."""
+    kv = 2.0 * np.pi / L * np.ones(3)
+    w = float(np.linalg.norm(kv))
+    n = kv / w
+    u = np.array([1.0, -1.0, 0.0]) / np.sqrt(2.0)
+    v = np.cross(n, u)
+    e = np.outer(u, u) - np.outer(v, v)
+
+    def fn(t, X, Y, Z):
+        ph = kv[0] * X + kv[1] * Y + kv[2] * Z - w * t
+        one = _ones(X) * (1.0 + 0 * t) * (1.0 + 0 * ph)
+        s = A * np.sin(ph)
+        st = -A * w * np.cos(ph)
+        gamma = np.zeros((3, 3) + np.shape(one), dtype=one.dtype)
+        K = np.zeros_like(gamma)
+        for a in range(3):
+            for b in range(3):
+                gamma[a, b] = (1.0 if a == b else 0.0) * one + e[a, b] * s
+                K[a, b] = -0.5 * e[a, b] * st
+        return gamma, K, one, [0 * one, 0 * one, 0 * one]
+    fn.period = 2.0 * np.pi / w
+    return fn
+
+
 # ------------------------------------------------------- ghosted blocks
 
 def ghosted_grid(mesh: Mesh, b: int):
