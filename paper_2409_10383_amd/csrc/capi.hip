@@ -32,9 +32,13 @@ struct z4c_pack {
     std::vector<XferItem> xfer;
     std::vector<ProlongItem> prol;
     std::vector<ProlongGroup> pgrp;
+    std::vector<ImageSlice> islice;
+    std::vector<int64_t> img_off;     // per block: offset of its coarse image, -1 if none
+    std::vector<int32_t> img_fstride;
+    int64_t image_elems = 0;
     std::vector<double> rw, pw, wtab;
     int64_t shadow_elems = 0;
-    size_t ws_xfer = 0, ws_prol = 0, ws_pgrp = 0, ws_w = 0, ws_shadow = 0;
+    size_t ws_xfer = 0, ws_prol = 0, ws_pgrp = 0, ws_islice = 0, ws_w = 0, ws_shadow = 0, ws_image = 0;
     size_t ws_first = 0, ws_feat = 0, ws_x = 0, ws_y = 0;
     std::vector<int32_t> first_work;
     int maxghost = 0;
@@ -174,26 +178,17 @@ struct Geo {
         return ((I[2] - B.ilo[2] + g) * (int64_t)B.E + (I[1] - B.ilo[1] + g)) * B.E + (I[0] - B.ilo[0] + g);
     }
     // restriction of coarse cell J (level l) from fine leaf F: window origin and weight sets
-    void restrict_window(int F, const int64_t J[3], int64_t& src, uint8_t d[3]) const
+    // coarse cell J (level of F minus one) in F's coarse image: local index
+    int64_t image_cell(int F, const int64_t J[3]) const
     {
-        const int nr = pk->p.nghost + 1;
         const z4c_block& FB = pk->blk[F];
-        int64_t s[3];
+        const int64_t m = FB.n / 2;
+        int64_t L[3];
         for (int a = 0; a < 3; ++a) {
-            const int64_t c = 2 * J[a];
-            int64_t st;
-            if (nr % 2 == 0) st = c - nr / 2 + 1;
-            else {
-                const double mid = FB.ilo[a] + 0.5 * FB.n;
-                st = ((double)(c + 1) < mid) ? c - (nr - 1) / 2 + 1 : c - (nr - 1) / 2;
-            }
-            const int64_t lo = FB.ilo[a], hi = FB.ilo[a] + FB.n - 1;
-            if (st < lo) st = lo;
-            if (st + nr - 1 > hi) st = hi - nr + 1;
-            s[a] = st;
-            d[a] = (uint8_t)(c + 1 - st);
+            L[a] = J[a] - FB.ilo[a] / 2;
+            if (L[a] < 0 || L[a] >= m) return -1;
         }
-        src = pk->bdev[F].off + cell(F, s);
+        return (L[2] * m + L[1]) * m + L[0];
     }
 };
 
@@ -223,10 +218,24 @@ int build_xlevel(z4c_pack* pk)
     const size_t esz = pk->p.precision == Z4C_FP64 ? 8 : 4;
     const int64_t per256 = 256 / (int64_t)esz;
     const int nb = (int)pk->blk.size();
+    pk->img_off.assign(nb, -1);
+    pk->img_fstride.assign(nb, 0);
+    // coarse image of fine block F (allocated on first use)
+    auto image_of = [&](int F) -> int64_t {
+        if (pk->img_off[F] < 0) {
+            const int64_t m = pk->blk[F].n / 2;
+            const int64_t fs = (m * m * m + per256 - 1) / per256 * per256;
+            pk->img_off[F] = pk->image_elems;
+            pk->img_fstride[F] = (int32_t)fs;
+            pk->image_elems += NF * fs;
+        }
+        return pk->img_off[F];
+    };
     for (int b = 0; b < nb; ++b) {
         const z4c_block& B = pk->blk[b];
         const BlockDev& D = pk->bdev[b];
         const int l = B.level, n = B.n, E = D.E;
+        if (D.slab > INT32_MAX) return Z4C_EUNSUPPORTED;
         // shadow box of this block at level l-1 (allocated on first use)
         int64_t S0[3];
         const int64_t SE = (n + 2 * g) / 2 + 2 * (np + 1) + 2;
@@ -248,10 +257,13 @@ int build_xlevel(z4c_pack* pk)
                     if (F >= 0) {
                         XferItem it;
                         it.dst = dcell;
-                        it.dst_stride = D.slab;
-                        geo.restrict_window(F, Gb, it.src, it.d);
-                        it.src_block = F;
+                        it.dst_stride = (int32_t)D.slab;
+                        const int64_t ic = geo.image_cell(F, Gb);
+                        if (ic < 0) return Z4C_EINVAL;
+                        it.src = image_of(F) + ic;
+                        it.src_stride = pk->img_fstride[F];
                         it.kind = 1;
+                        it.pad = 0;
                         pk->xfer.push_back(it);
                         continue;
                     }
@@ -296,19 +308,21 @@ int build_xlevel(z4c_pack* pk)
                                 geo.bc(l - 1, Kb);
                                 XferItem it;
                                 it.dst = shoff + loc;
-                                it.dst_stride = fstride;
+                                it.dst_stride = (int32_t)fstride;
                                 it.kind = 2;
-                                it.d[0] = it.d[1] = it.d[2] = 0;
+                                it.pad = 0;
                                 const int Cb = geo.leaf(l - 1, Kb);
                                 if (Cb >= 0) {
                                     it.src = pk->bdev[Cb].off + geo.cell(Cb, Kb);
-                                    it.src_block = Cb;
+                                    it.src_stride = (int32_t)pk->bdev[Cb].slab;
                                 } else {
                                     const int64_t K2[3] = {2 * Kb[0], 2 * Kb[1], 2 * Kb[2]};
                                     const int Fb = geo.leaf(l, K2);
                                     if (Fb < 0) return Z4C_EINVAL;  // would need a level two away
-                                    geo.restrict_window(Fb, Kb, it.src, it.d);
-                                    it.src_block = Fb;
+                                    const int64_t ic = geo.image_cell(Fb, Kb);
+                                    if (ic < 0) return Z4C_EINVAL;
+                                    it.src = image_of(Fb) + ic;
+                                    it.src_stride = pk->img_fstride[Fb];
                                     it.kind = 3;
                                 }
                                 pk->xfer.push_back(it);
@@ -344,6 +358,29 @@ int build_xlevel(z4c_pack* pk)
                         pk->prol.push_back(pi);
                     }
                 }
+    }
+    // image restriction work: per source block, coarse z-slices split into
+    // row chunks that fit the LDS budget
+    for (int F = 0; F < nb; ++F) {
+        if (pk->img_off[F] < 0) continue;
+        const int m = pk->blk[F].n / 2;
+        if (pk->blk[F].ilo[0] % 2 || pk->blk[F].ilo[1] % 2 || pk->blk[F].ilo[2] % 2) return Z4C_EINVAL;
+        if (pk->blk[F].n < np) return Z4C_EUNSUPPORTED;
+        int cy = m;
+        while (cy > 1 && ((int64_t)m * (2 * cy + np) * np > RI_XMAX || (int64_t)m * cy * np > RI_YMAX)) cy /= 2;
+        if ((int64_t)m * (2 * cy + np) * np > RI_XMAX || (int64_t)m * cy * np > RI_YMAX) return Z4C_EUNSUPPORTED;
+        for (int kz = 0; kz < m; ++kz)
+            for (int y0 = 0; y0 < m; y0 += cy) {
+                ImageSlice sl;
+                sl.img = pk->img_off[F];
+                sl.block = F;
+                sl.fstride = pk->img_fstride[F];
+                sl.kz = (int16_t)kz;
+                sl.y0 = (int16_t)y0;
+                sl.ny = (int16_t)std::min(cy, m - y0);
+                sl.pad = 0;
+                pk->islice.push_back(sl);
+            }
     }
     return Z4C_OK;
 }
@@ -525,6 +562,8 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
     pk->ws_pgrp = o;   o = align256(o + sizeof(ProlongGroup) * pk->pgrp.size());
     pk->ws_w = o;      o = align256(o + sizeof(double) * 80);
     pk->ws_shadow = o; o = align256(o + esz * (size_t)pk->shadow_elems);
+    pk->ws_islice = o; o = align256(o + sizeof(ImageSlice) * pk->islice.size());
+    pk->ws_image = o;  o = align256(o + esz * (size_t)pk->image_elems);
     pk->ws_total = o;
     pk->part_host.resize(16 * pk->work.size());
     pk->first_work.assign(nblocks + 1, 0);
@@ -586,6 +625,9 @@ int z4c_pack_bind(z4c_pack* pk, void* const regs[Z4C_NREG], void* workspace, siz
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !pk->prol.empty())
         e = hipMemcpyAsync(ws + pk->ws_prol, pk->prol.data(), sizeof(ProlongItem) * pk->prol.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !pk->islice.empty())
+        e = hipMemcpyAsync(ws + pk->ws_islice, pk->islice.data(), sizeof(ImageSlice) * pk->islice.size(),
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !pk->pgrp.empty())
         e = hipMemcpyAsync(ws + pk->ws_pgrp, pk->pgrp.data(), sizeof(ProlongGroup) * pk->pgrp.size(),
@@ -667,6 +709,9 @@ int z4c_fill_ghosts(z4c_pack* pk, int32_t reg, void* stream)
         XlevelArgs x;
         x.reg = pk->reg[reg];
         x.shadow = pk->ws + pk->ws_shadow;
+        x.image = pk->ws + pk->ws_image;
+        x.islice = reinterpret_cast<const ImageSlice*>(pk->ws + pk->ws_islice);
+        x.nislice = (int64_t)pk->islice.size();
         x.blocks = a.blocks;
         x.xfer = reinterpret_cast<const XferItem*>(pk->ws + pk->ws_xfer);
         x.prol = reinterpret_cast<const ProlongItem*>(pk->ws + pk->ws_prol);

@@ -79,40 +79,86 @@ __global__ __launch_bounds__(256) void k_fill_same(const FillArgs a)
     for (int f = 0; f < NF; ++f) r[d + f * B.slab] = r[so + f * SB.slab];
 }
 
-// copies and restrictions (reads active cells only)
+// Restriction window of coarse cell kc (0 <= kc < n/2) inside a fine block
+// of n active cells per axis: first fine cell o of the np-point window and
+// the weight set d (evaluation point at the fine face o + d).  Centred where
+// it fits; for odd np the extra point goes towards the block's interior;
+// clamped to the block's active cells.
+__device__ __forceinline__ void rwin(int kc, int n, int np, int& o, int& d)
+{
+    const int c = 2 * kc;
+    int st = (np % 2 == 0) ? c - np / 2 + 1 : ((2 * kc + 1 < n / 2) ? c - (np - 1) / 2 + 1 : c - (np - 1) / 2);
+    st = st < 0 ? 0 : st;
+    st = st + np > n ? n - np : st;
+    o = st;
+    d = c + 1 - st;
+}
+
+// Coarse image of a fine block: separable x, y, z passes through LDS (the
+// same association order as a direct triple sum: x innermost).
+template <class T>
+__global__ __launch_bounds__(256) void k_restrict_image(const XlevelArgs a)
+{
+    __shared__ double X[RI_XMAX];
+    __shared__ double Y[RI_YMAX];
+    const ImageSlice sl = a.islice[blockIdx.x];
+    const BlockDev F = a.blocks[sl.block];
+    const int n = F.n, m = n >> 1, np = a.npts, E = F.E, g = (E - n) >> 1;
+    const int t = threadIdx.x, ny = sl.ny;
+    int oz, dz, oy0, dy0, oy1, dy1;
+    rwin(sl.kz, n, np, oz, dz);
+    rwin(sl.y0, n, np, oy0, dy0);
+    rwin(sl.y0 + ny - 1, n, np, oy1, dy1);
+    const int R = oy1 + np - oy0;    // fine rows staged per plane
+    const T* base = (const T*)a.reg + F.off + ((int64_t)(oz + g) * E + (oy0 + g)) * E + g;
+    T* img = (T*)a.image + sl.img;
+    const double* wz = a.rw + 8 * dz;
+    const int nx = m * R * np, nyq = m * ny * np, nz = m * ny;
+    for (int f = 0; f < NF; ++f) {
+        const T* p = base + (int64_t)f * F.slab;
+        for (int q = t; q < nx; q += 256) {
+            const int kx = q % m, r = (q / m) % R, pz = q / (m * R);
+            int ox, dx;
+            rwin(kx, n, np, ox, dx);
+            const T* row = p + ((int64_t)pz * E + r) * E + ox;
+            const double* wx = a.rw + 8 * dx;
+            double s = 0.0;
+            for (int ix = 0; ix < np; ++ix) s += wx[ix] * (double)row[ix];
+            X[q] = s;
+        }
+        __syncthreads();
+        for (int q = t; q < nyq; q += 256) {
+            const int kx = q % m, cy = (q / m) % ny, pz = q / (m * ny);
+            int oy, dy;
+            rwin(sl.y0 + cy, n, np, oy, dy);
+            const double* wy = a.rw + 8 * dy;
+            double s = 0.0;
+            for (int jy = 0; jy < np; ++jy) s += wy[jy] * X[(pz * R + (oy - oy0 + jy)) * m + kx];
+            Y[q] = s;
+        }
+        __syncthreads();
+        // the next field's x-pass writes X only; Y is rewritten after the
+        // next barrier, which every thread reaches after this z-pass
+        for (int q = t; q < nz; q += 256) {
+            const int kx = q % m, cy = q / m;
+            double s = 0.0;
+            for (int kz = 0; kz < np; ++kz) s += wz[kz] * Y[(kz * ny + cy) * m + kx];
+            img[(int64_t)f * sl.fstride + ((int64_t)sl.kz * m + (sl.y0 + cy)) * m + kx] = (T)s;
+        }
+    }
+}
+
+// copies into ghost cells and shadow boxes (sources: active cells, images)
 template <class T>
 __global__ __launch_bounds__(256) void k_xfer(const XlevelArgs a)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= a.nxfer) return;
     const XferItem it = a.xfer[q];
-    const BlockDev S = a.blocks[it.src_block];
-    const T* __restrict__ src = (const T*)a.reg + it.src;
+    const T* __restrict__ src = (const T*)((it.kind & 1) ? a.image : a.reg) + it.src;
     T* dst = (T*)((it.kind & 2) ? a.shadow : a.reg) + it.dst;
-    const int np = a.npts;
-    if (!(it.kind & 1)) {
-        for (int f = 0; f < NF; ++f) dst[f * it.dst_stride] = src[f * S.slab];
-        return;
-    }
-    const double* wx = a.rw + 8 * it.d[0];
-    const double* wy = a.rw + 8 * it.d[1];
-    const double* wz = a.rw + 8 * it.d[2];
-    const int64_t E = S.E;
-    for (int f = 0; f < NF; ++f) {
-        const T* p = src + f * S.slab;
-        double acc = 0.0;
-        for (int kz = 0; kz < np; ++kz) {
-            double az = 0.0;
-            for (int jy = 0; jy < np; ++jy) {
-                const T* row = p + (kz * E + jy) * E;
-                double ay = 0.0;
-                for (int ix = 0; ix < np; ++ix) ay += wx[ix] * (double)row[ix];
-                az += wy[jy] * ay;
-            }
-            acc += wz[kz] * az;
-        }
-        dst[f * it.dst_stride] = (T)acc;
-    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) dst[(int64_t)f * it.dst_stride] = src[(int64_t)f * it.src_stride];
 }
 
 // prolongation of fine ghosts from the shadow boxes
@@ -199,10 +245,12 @@ hipError_t launch_xlevel(int prec, const XlevelArgs& a, hipStream_t s)
     const unsigned gx = (unsigned)((a.nxfer + 255) / 256), gp = (unsigned)((a.nprol + 255) / 256);
     const unsigned gg = (unsigned)((a.npgrp + 255) / 256);
     if (prec == 0) {
+        if (a.nislice) hipLaunchKernelGGL(k_restrict_image<double>, dim3((unsigned)a.nislice), dim3(256), 0, s, a);
         if (gx) hipLaunchKernelGGL(k_xfer<double>, dim3(gx), dim3(256), 0, s, a);
         if (gp) hipLaunchKernelGGL(k_prolong<double>, dim3(gp), dim3(256), 0, s, a);
         if (gg) hipLaunchKernelGGL(k_prolong_group<double>, dim3(gg), dim3(256), 0, s, a);
     } else {
+        if (a.nislice) hipLaunchKernelGGL(k_restrict_image<float>, dim3((unsigned)a.nislice), dim3(256), 0, s, a);
         if (gx) hipLaunchKernelGGL(k_xfer<float>, dim3(gx), dim3(256), 0, s, a);
         if (gp) hipLaunchKernelGGL(k_prolong<float>, dim3(gp), dim3(256), 0, s, a);
         if (gg) hipLaunchKernelGGL(k_prolong_group<float>, dim3(gg), dim3(256), 0, s, a);

@@ -34,16 +34,21 @@ struct FillArgs {
     int32_t maxghost;         // ghost cells of the largest block
 };
 
+// LDS budget of the image restriction (doubles): x-pass and y-pass partials
+constexpr int RI_XMAX = 6144, RI_YMAX = 2048;
+
 struct XlevelArgs {
     void* reg;                // register being filled
     void* shadow;             // shadow boxes (same element type)
+    void* image;              // coarse images of restriction sources (same element type)
+    const ImageSlice* islice;
     const BlockDev* blocks;
     const XferItem* xfer;
     const ProlongItem* prol;
     const ProlongGroup* pgrp;
     const double* rw;         // restriction weights [8][8]: set d, point q
     const double* pw;         // prolongation weights [2][8]: parity, point q
-    int64_t nxfer, nprol, npgrp;
+    int64_t nxfer, nprol, npgrp, nislice;
     int32_t npts;             // g + 1
 };
 

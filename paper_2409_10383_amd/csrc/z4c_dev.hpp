@@ -44,16 +44,28 @@ struct LookupDev {
 };
 
 // cross-level ghost fill (refinement boundaries)
-// A transfer writes 22 values: a copy of one active cell, or the Lagrange
-// restriction (n = g+1 points per axis) of a window of fine active cells,
-// into a ghost cell of a register or into a block's coarse shadow box.
+// Restriction: the value of coarse cell K restricted from fine block F (the
+// leaf that owns fine cell 2K) is a Lagrange interpolation (n = g+1 points
+// per axis) over a window of F's active cells that depends only on K's
+// position inside F.  Each fill first restricts every source block as a
+// whole into its coarse image; a transfer then copies 22 values, from an
+// active cell or an image cell, into a ghost cell of a register or into a
+// block's coarse shadow box.
 struct XferItem {
     int64_t dst;          // element offset of field 0 at the destination
-    int64_t dst_stride;   // element stride between fields at the destination
-    int64_t src;          // element offset (field 0) of the source cell / window origin
-    int32_t src_block;    // source block (field stride and row length)
-    uint8_t kind;         // bit0: restriction (else copy); bit1: destination is a shadow box
-    uint8_t d[3];         // per-axis restriction weight set
+    int64_t src;          // element offset of field 0 at the source
+    int32_t dst_stride;   // element stride between fields at the destination
+    int32_t src_stride;   // element stride between fields at the source
+    int32_t kind;         // bit0: source is a coarse image; bit1: destination is a shadow box
+    int32_t pad;
+};
+// One workgroup of the image restriction: coarse rows y0 .. y0+ny-1 of
+// coarse z-slice kz of block `block`, all x.
+struct ImageSlice {
+    int64_t img;          // element offset of the block's image (field 0)
+    int32_t block;
+    int32_t fstride;      // field stride of the image (elements)
+    int16_t kz, y0, ny, pad;
 };
 // A prolongation fills one fine ghost cell from the (g+1)^3 coarse values
 // of its block's shadow box.
