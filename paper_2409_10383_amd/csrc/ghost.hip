@@ -96,14 +96,14 @@ __device__ __forceinline__ void rwin(int kc, int n, int np, int& o, int& d)
 
 // Coarse image of a fine block: separable x, y, z passes through LDS (the
 // same association order as a direct triple sum: x innermost).
-template <class T>
+template <class T, int NP>
 __global__ __launch_bounds__(256) void k_restrict_image(const XlevelArgs a)
 {
     __shared__ double X[RI_XMAX];
     __shared__ double Y[RI_YMAX];
     const ImageSlice sl = a.islice[blockIdx.x];
     const BlockDev F = a.blocks[sl.block];
-    const int n = F.n, m = n >> 1, np = a.npts, E = F.E, g = (E - n) >> 1;
+    const int n = F.n, m = n >> 1, np = NP ? NP : a.npts, E = F.E, g = (E - n) >> 1;
     const int t = threadIdx.x, ny = sl.ny;
     int oz, dz, oy0, dy0, oy1, dy1;
     rwin(sl.kz, n, np, oz, dz);
@@ -123,6 +123,7 @@ __global__ __launch_bounds__(256) void k_restrict_image(const XlevelArgs a)
             const T* row = p + ((int64_t)pz * E + r) * E + ox;
             const double* wx = a.rw + 8 * dx;
             double s = 0.0;
+#pragma unroll
             for (int ix = 0; ix < np; ++ix) s += wx[ix] * (double)row[ix];
             X[q] = s;
         }
@@ -133,6 +134,7 @@ __global__ __launch_bounds__(256) void k_restrict_image(const XlevelArgs a)
             rwin(sl.y0 + cy, n, np, oy, dy);
             const double* wy = a.rw + 8 * dy;
             double s = 0.0;
+#pragma unroll
             for (int jy = 0; jy < np; ++jy) s += wy[jy] * X[(pz * R + (oy - oy0 + jy)) * m + kx];
             Y[q] = s;
         }
@@ -142,6 +144,7 @@ __global__ __launch_bounds__(256) void k_restrict_image(const XlevelArgs a)
         for (int q = t; q < nz; q += 256) {
             const int kx = q % m, cy = q / m;
             double s = 0.0;
+#pragma unroll
             for (int kz = 0; kz < np; ++kz) s += wz[kz] * Y[(kz * ny + cy) * m + kx];
             img[(int64_t)f * sl.fstride + ((int64_t)sl.kz * m + (sl.y0 + cy)) * m + kx] = (T)s;
         }
@@ -195,7 +198,7 @@ __global__ __launch_bounds__(256) void k_prolong(const XlevelArgs a)
 
 // grouped prolongation: one coarse parent, up to 8 fine children, separable
 // (x, then y, then z) over the union stencil
-template <class T>
+template <class T, int NP>
 __global__ __launch_bounds__(256) void k_prolong_group(const XlevelArgs a)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -204,7 +207,7 @@ __global__ __launch_bounds__(256) void k_prolong_group(const XlevelArgs a)
     const BlockDev B = a.blocks[it.block];
     const T* __restrict__ sh = (const T*)a.shadow + it.sh;
     T* dst = (T*)a.reg + it.dst;
-    const int np = a.npts;
+    const int np = NP ? NP : a.npts;
     const int even = (np % 2 == 0);
     const int nu = np + even;          // union stencil points per axis
     const int64_t se = it.se, E = B.E;
@@ -213,11 +216,14 @@ __global__ __launch_bounds__(256) void k_prolong_group(const XlevelArgs a)
     for (int f = 0; f < NF; ++f) {
         const T* p = sh + (int64_t)f * it.fstride;
         double acc[2][2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
+#pragma unroll 1
         for (int kz = 0; kz < nu; ++kz) {
             double ay[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
             for (int jy = 0; jy < nu; ++jy) {
                 const T* row = p + (kz * se + jy) * se;
                 double ax0 = 0.0, ax1 = 0.0;
+#pragma unroll
                 for (int ix = 0; ix < nu; ++ix) {
                     const double v = (double)row[ix];
                     if (ix < np) ax0 += w0[ix] * v;
@@ -240,21 +246,33 @@ __global__ __launch_bounds__(256) void k_prolong_group(const XlevelArgs a)
     }
 }
 
-hipError_t launch_xlevel(int prec, const XlevelArgs& a, hipStream_t s)
+template <class T, int NP>
+static void launch_xlevel_np(const XlevelArgs& a, hipStream_t s)
 {
     const unsigned gx = (unsigned)((a.nxfer + 255) / 256), gp = (unsigned)((a.nprol + 255) / 256);
     const unsigned gg = (unsigned)((a.npgrp + 255) / 256);
-    if (prec == 0) {
-        if (a.nislice) hipLaunchKernelGGL(k_restrict_image<double>, dim3((unsigned)a.nislice), dim3(256), 0, s, a);
-        if (gx) hipLaunchKernelGGL(k_xfer<double>, dim3(gx), dim3(256), 0, s, a);
-        if (gp) hipLaunchKernelGGL(k_prolong<double>, dim3(gp), dim3(256), 0, s, a);
-        if (gg) hipLaunchKernelGGL(k_prolong_group<double>, dim3(gg), dim3(256), 0, s, a);
-    } else {
-        if (a.nislice) hipLaunchKernelGGL(k_restrict_image<float>, dim3((unsigned)a.nislice), dim3(256), 0, s, a);
-        if (gx) hipLaunchKernelGGL(k_xfer<float>, dim3(gx), dim3(256), 0, s, a);
-        if (gp) hipLaunchKernelGGL(k_prolong<float>, dim3(gp), dim3(256), 0, s, a);
-        if (gg) hipLaunchKernelGGL(k_prolong_group<float>, dim3(gg), dim3(256), 0, s, a);
+    if (a.nislice) hipLaunchKernelGGL((k_restrict_image<T, NP>), dim3((unsigned)a.nislice), dim3(256), 0, s, a);
+    if (gx) hipLaunchKernelGGL(k_xfer<T>, dim3(gx), dim3(256), 0, s, a);
+    if (gp) hipLaunchKernelGGL(k_prolong<T>, dim3(gp), dim3(256), 0, s, a);
+    if (gg) hipLaunchKernelGGL((k_prolong_group<T, NP>), dim3(gg), dim3(256), 0, s, a);
+}
+
+template <class T>
+static void launch_xlevel_t(const XlevelArgs& a, hipStream_t s)
+{
+    // stencil widths of the 4th/6th/8th-order ghost depths get unrolled kernels
+    switch (a.npts) {
+    case 4: launch_xlevel_np<T, 4>(a, s); break;
+    case 5: launch_xlevel_np<T, 5>(a, s); break;
+    case 6: launch_xlevel_np<T, 6>(a, s); break;
+    default: launch_xlevel_np<T, 0>(a, s); break;
     }
+}
+
+hipError_t launch_xlevel(int prec, const XlevelArgs& a, hipStream_t s)
+{
+    if (prec == 0) launch_xlevel_t<double>(a, s);
+    else launch_xlevel_t<float>(a, s);
     return hipGetLastError();
 }
 

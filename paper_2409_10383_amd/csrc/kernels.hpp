@@ -35,7 +35,7 @@ struct FillArgs {
 };
 
 // LDS budget of the image restriction (doubles): x-pass and y-pass partials
-constexpr int RI_XMAX = 6144, RI_YMAX = 2048;
+constexpr int RI_XMAX = 4096, RI_YMAX = 1536;
 
 struct XlevelArgs {
     void* reg;                // register being filled
