@@ -23,6 +23,8 @@ FP64, FP32_MIXED = 0, 1
 TERM_PHYS, TERM_GAUGE, TERM_ADVECT, TERM_DISSIP, TERM_ALL = 1, 2, 4, 8, 15
 FLAG_ENFORCE, FLAG_CHECK_FINITE, FLAG_GRAPH = 1, 2, 4
 CRIT_CHI_MIN, CRIT_DCHI_MAX, CRIT_RADIUS = 0, 1, 2
+# tile shapes of the stage-kernel variants (x, y, z active cells per workgroup)
+TILE_SHAPES = [(8, 8, 4), (16, 4, 4), (8, 4, 8), (16, 8, 2)]
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "ENONFINITE",
           -6: "EUNSUPPORTED"}
 

@@ -223,7 +223,7 @@ __device__ __forceinline__ void z4c_algebra(const ParamsDev& P, C chi, const C (
             for (int k = 0; k < 3; ++k) s += gdn[S(i, k)] * dbe[j][k] + gdn[S(j, k)] * dbe[i][k];
             rhs[F_GXX + p] = s;
         }
-        rhs[F_KH] = -trDDa + al * (AA + K * K / (C)3) + (C)(P.kappa1 * (1.0 - P.kappa2)) * al * Th;
+        rhs[F_KH] = -trDDa + al * (AA + K * K * (C)(1.0 / 3.0)) + (C)(P.kappa1 * (1.0 - P.kappa2)) * al * Th;
         C X[6], trX = 0;
 #pragma unroll
         for (int p = 0; p < 6; ++p) {
@@ -233,7 +233,7 @@ __device__ __forceinline__ void z4c_algebra(const ParamsDev& P, C chi, const C (
 #pragma unroll
         for (int p = 0; p < 6; ++p) {
             const int i = SA(p), j = SB(p);
-            C s = chi * (X[p] - gdn[p] * trX / (C)3);
+            C s = chi * (X[p] - gdn[p] * trX * (C)(1.0 / 3.0));
             const C AgA = Am[i][0] * A[S(0, j)] + Am[i][1] * A[S(1, j)] + Am[i][2] * A[S(2, j)];
             s += al * (K * A[p] - (C)2 * AgA);
 #pragma unroll
@@ -244,13 +244,13 @@ __device__ __forceinline__ void z4c_algebra(const ParamsDev& P, C chi, const C (
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             C s = (C)(2.0 / 3.0) * Gd[i] * divb - (Gd[0] * dbe[0][i] + Gd[1] * dbe[1][i] + Gd[2] * dbe[2][i]);
-            s += Lb[i] + (gu[S(i, 0)] * Bj[0] + gu[S(i, 1)] * Bj[1] + gu[S(i, 2)] * Bj[2]) / (C)3;
+            s += Lb[i] + (gu[S(i, 0)] * Bj[0] + gu[S(i, 1)] * Bj[1] + gu[S(i, 2)] * Bj[2]) * (C)(1.0 / 3.0);
             s -= (C)2 * (Au[S(i, 0)] * dal[0] + Au[S(i, 1)] * dal[1] + Au[S(i, 2)] * dal[2]);
             C t = 0;
 #pragma unroll
             for (int p = 0; p < 6; ++p) t += (C)SW(p) * Gu[i][p] * Au[p];
             t -= (C)1.5 * ic * (Au[S(i, 0)] * dchi[0] + Au[S(i, 1)] * dchi[1] + Au[S(i, 2)] * dchi[2]);
-            t -= (gu[S(i, 0)] * eK[0] + gu[S(i, 1)] * eK[1] + gu[S(i, 2)] * eK[2]) / (C)3;
+            t -= (gu[S(i, 0)] * eK[0] + gu[S(i, 1)] * eK[1] + gu[S(i, 2)] * eK[2]) * (C)(1.0 / 3.0);
             s += (C)2 * al * t;
             s -= (C)2 * al * (C)P.kappa1 * (Gam[i] - Gd[i]);
             rhs[F_GAMX + i] = s;
@@ -397,17 +397,18 @@ __device__ __forceinline__ void enforce_zone(double* u, const ParamsDev& P)
     g0 *= s; g1 *= s; g2 *= s; g3 *= s; g4 *= s; g5 *= s;
     const double c0 = g3 * g5 - g4 * g4, c1 = g2 * g4 - g1 * g5, c2 = g1 * g4 - g2 * g3;
     const double d = g0 * c0 + g1 * c1 + g2 * c2;
-    const double gu0 = c0 / d, gu1 = c1 / d, gu2 = c2 / d, gu3 = (g0 * g5 - g2 * g2) / d,
-                 gu4 = (g1 * g2 - g0 * g4) / d, gu5 = (g0 * g3 - g1 * g1) / d;
+    const double id = 1.0 / d;
+    const double gu0 = c0 * id, gu1 = c1 * id, gu2 = c2 * id, gu3 = (g0 * g5 - g2 * g2) * id,
+                 gu4 = (g1 * g2 - g0 * g4) * id, gu5 = (g0 * g3 - g1 * g1) * id;
     const double tr = gu0 * u[F_AXX] + gu3 * u[F_AYY] + gu5 * u[F_AZZ] +
                       2.0 * (gu1 * u[F_AXY] + gu2 * u[F_AXZ] + gu4 * u[F_AYZ]);
     u[F_GXX] = g0; u[F_GXY] = g1; u[F_GXZ] = g2; u[F_GYY] = g3; u[F_GYZ] = g4; u[F_GZZ] = g5;
-    u[F_AXX] -= g0 * tr / 3.0;
-    u[F_AXY] -= g1 * tr / 3.0;
-    u[F_AXZ] -= g2 * tr / 3.0;
-    u[F_AYY] -= g3 * tr / 3.0;
-    u[F_AYZ] -= g4 * tr / 3.0;
-    u[F_AZZ] -= g5 * tr / 3.0;
+    u[F_AXX] -= g0 * tr * (1.0 / 3.0);
+    u[F_AXY] -= g1 * tr * (1.0 / 3.0);
+    u[F_AXZ] -= g2 * tr * (1.0 / 3.0);
+    u[F_AYY] -= g3 * tr * (1.0 / 3.0);
+    u[F_AYZ] -= g4 * tr * (1.0 / 3.0);
+    u[F_AZZ] -= g5 * tr * (1.0 / 3.0);
     if (u[F_CHI] < P.chi_floor) u[F_CHI] = P.chi_floor;
     if (u[F_ALPHA] < P.alpha_floor) u[F_ALPHA] = P.alpha_floor;
 }
