@@ -33,6 +33,44 @@ template <int N, int TX, int TY, int TZ> struct TileGeom {
     static constexpr int NDY = TX * TY * DXZ;       // d_y f on a z halo
 };
 
+// LDS per workgroup: NBUF staged-field buffers, the mixed-derivative
+// intermediates and the per-zone advection + dissipation slots.  Two
+// buffers (the next field streams in while the current one is used) when
+// they fit in a CU's 160 KB, else one.
+template <class G, class C> struct StageLds {
+    static constexpr int REST = (G::NDX + G::NDY + NF * 256) * (int)sizeof(C);
+    static constexpr int NBUF = (2 * G::NS * (int)sizeof(C) + REST <= 160 * 1024) ? 2 : 1;
+};
+
+typedef __attribute__((address_space(1))) const void* gptr_t;
+typedef __attribute__((address_space(3))) void* lptr_t;
+
+// Asynchronous copy of one staged field (global -> LDS, no registers): the
+// staged tile is dense in LDS (x fastest), so slot u of S bytes lands at
+// byte S*u; lane l of a wave writes S bytes at the wave's LDS base + S*l.
+// soff holds the byte offset (from the tile origin in the ghosted block) of
+// the first byte of each of this thread's slots.
+template <int S, int NSLOT, int NR>
+__device__ __forceinline__ void dma_field(const char* gbase, char* lbase, const int (&soff)[NR])
+{
+    const int t = threadIdx.x, w = t >> 6;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        if (r * 256 + t < NSLOT) {
+            const gptr_t src = (gptr_t)(gbase + soff[r]);
+            const lptr_t dst = (lptr_t)(lbase + (r * 256 + w * 64) * S);
+            if constexpr (S == 16) __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+            else __builtin_amdgcn_global_load_lds(src, dst, 4, 0, 0);
+        }
+}
+
+// wait for this wave's outstanding vector memory operations (the LDS
+// copies above count there), before the barrier that publishes them
+__device__ __forceinline__ void wait_vmem()
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt unconstrained
+}
+
 // one axis of a staged field: centred d1, d2 (both optional) and the
 // advection + dissipation contribution; no 1/h factors
 // va is the advection speed along the axis (0 when advection is off) and
@@ -80,7 +118,7 @@ template <int N, class T, class C, int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_stage(const StageArgs a)
 {
     using G = TileGeom<N, TX, TY, TZ>;
-    __shared__ C tile[G::NS];
+    __shared__ __align__(16) C tile[StageLds<G, C>::NBUF * G::NS];
     __shared__ C dxs[G::NDX];
     __shared__ C dys[G::NDY];
     __shared__ C adks[NF * 256];   // advection + dissipation, per field and zone
@@ -120,6 +158,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     // staged-tile index of this zone and its strides
     const int c = ((tz + R) * SY + (ty + R)) * SX + (tx + R);
     const int sxy = SX * SY;
+    C* cur = tile;   // LDS buffer holding the field being processed
 
     // origin of the staged tile (tile + halo R) in the ghosted block
     const int64_t base0 = ((int64_t)(w.k0 - R + g) * E + (w.j0 - R + g)) * E + (w.i0 - R + g);
@@ -142,10 +181,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     auto first_pass = [&]() {
 #pragma unroll
         for (int r = 0; r < NQX; ++r)
-            if (t + 256 * r < G::NDX) dxs[t + 256 * r] = fd1<N, C>(tile + ccx[r], 1);
+            if (t + 256 * r < G::NDX) dxs[t + 256 * r] = fd1<N, C>(cur + ccx[r], 1);
 #pragma unroll
         for (int r = 0; r < NQY; ++r)
-            if (t + 256 * r < G::NDY) dys[t + 256 * r] = fd1<N, C>(tile + ccy[r], SX);
+            if (t + 256 * r < G::NDY) dys[t + 256 * r] = fd1<N, C>(cur + ccy[r], SX);
     };
     // mixed derivatives of the staged field at this zone: xy, xz, yz
     auto mixed = [&](C& mxy, C& mxz, C& myz) {
@@ -192,7 +231,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             C x1, x2;
-            axis_pass<N, C, WD1, WD2>(tile, c, st3[d], a_on ? be[d] : (C)0, sig, x1, x2, ad);
+            axis_pass<N, C, WD1, WD2>(cur, c, st3[d], a_on ? be[d] : (C)0, sig, x1, x2, ad);
             if (WD1) d1[d] = x1 * ih;
             if (WD2) d2[d] = x2 * ih2;
         }
@@ -201,29 +240,43 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     using T1 = std::integral_constant<bool, true>;
     using F0 = std::integral_constant<bool, false>;
 
-    // ---- the 22 fields through LDS, in the order below; the global loads of
-    // the next field are issued before the current one is processed, so
-    // their latency overlaps the stencil work
-    constexpr int NPRE = (G::NS + 255) / 256;
-    T pre[NPRE];
-    int soff[NPRE];  // offsets of this thread's staged cells from the tile origin
+    // ---- the 22 fields stream through LDS in the order below.  Each field's
+    // staged tile is copied global -> LDS asynchronously (no registers); with
+    // two buffers the next field's copy is issued before the current field is
+    // processed, so its latency overlaps the stencil work.
+    constexpr int NBUF = StageLds<G, C>::NBUF;
+    constexpr int SLOT = sizeof(T) == 8 ? 16 : 4;        // bytes per lane and copy
+    constexpr int NSLOT = G::NS * (int)sizeof(T) / SLOT;
+    constexpr int NRS = (NSLOT + 255) / 256;
+    // 16-byte FP64 copies need a 16-byte aligned tile origin: E, every field
+    // base and the tile's x origin are even when the ghost depth and the halo
+    // differ by an even count; otherwise FP64 fields go as 4-byte halves
+    const bool wide = sizeof(T) == 4 || ((g - R) & 1) == 0;
+    int soff[NRS];
 #pragma unroll
-    for (int r = 0; r < NPRE; ++r) {
-        const int q = t + 256 * r;
+    for (int r = 0; r < NRS; ++r) {
+        const int q = (r * 256 + t) * (SLOT / (int)sizeof(T));   // first element of the slot
         const int x = q % SX, y = (q / SX) % SY, z = q / sxy;
-        soff[r] = (z * E + y) * E + x;
+        soff[r] = ((z * E + y) * E + x) * (int)sizeof(T);
     }
-    auto fetch = [&](int f) {
-        const T* __restrict__ p = srcb + f * slab + base0;
-#pragma unroll
-        for (int r = 0; r < NPRE; ++r)
-            if (t + 256 * r < G::NS) pre[r] = p[soff[r]];
-    };
-    auto put = [&]() {
-#pragma unroll
-        for (int r = 0; r < NPRE; ++r) {
-            const int q = t + 256 * r;
-            if (q < G::NS) tile[q] = (C)pre[r];
+    auto issue = [&](int f, C* buf) {
+        const char* gb = (const char*)(srcb + f * slab + base0);
+        if (wide) {
+            dma_field<SLOT, NSLOT, NRS>(gb, (char*)buf, soff);
+        } else {
+            constexpr int NS4 = G::NS * (int)sizeof(T) / 4, NR4 = (NS4 + 255) / 256;
+            const int wv = t >> 6;
+#pragma unroll 4
+            for (int r = 0; r < NR4; ++r) {
+                const int u = r * 256 + t;
+                if (u < NS4) {
+                    const int q = u * 4 / (int)sizeof(T), hb = (u * 4) % (int)sizeof(T);
+                    const int x = q % SX, y = (q / SX) % SY, z = q / sxy;
+                    const int off = ((z * E + y) * E + x) * (int)sizeof(T) + hb;
+                    __builtin_amdgcn_global_load_lds((gptr_t)(gb + off),
+                                                     (lptr_t)((char*)buf + (r * 256 + wv * 64) * 4), 4, 0, 0);
+                }
+            }
         }
     };
     // slot -> field: g~ (6), chi, alpha, beta (3), Gamma~ (3), Khat, Theta, A~ (6)
@@ -231,13 +284,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
         return sl < 6 ? F_GXX + sl : sl == 6 ? F_CHI : sl == 7 ? F_ALPHA : sl < 11 ? F_BETAX + (sl - 8)
              : sl < 14 ? F_GAMX + (sl - 11) : sl == 14 ? F_KH : sl == 15 ? F_TH : F_AXX + (sl - 16);
     };
-    fetch(field_of(0));
+    issue(field_of(0), tile);
 #pragma unroll 1
     for (int sl = 0; sl < NF; ++sl) {
-        __syncthreads();
-        put();
-        __syncthreads();
-        if (sl + 1 < NF) fetch(field_of(sl + 1));
+        cur = (NBUF == 2 && (sl & 1)) ? tile + G::NS : tile;
+        wait_vmem();
+        __syncthreads();   // field sl in LDS; every wave is done with field sl-1
+        if (NBUF == 2 && sl + 1 < NF) issue(field_of(sl + 1), (sl & 1) ? tile : tile + G::NS);
         if (sl < 6) {
             // conformal metric: first derivatives, Ricci second-derivative term
             const int p = sl;
@@ -325,9 +378,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 C x1, x2;
-                axis_pass<N, C, false, false>(tile, c, st3[d], adv ? be[d] : (C)0, sig, x1, x2, ad);
+                axis_pass<N, C, false, false>(cur, c, st3[d], adv ? be[d] : (C)0, sig, x1, x2, ad);
             }
             put_adk(F_AXX + (sl - 16), ad * ih);
+        }
+        if (NBUF == 1 && sl + 1 < NF) {
+            __syncthreads();   // every wave is done with the single buffer
+            issue(field_of(sl + 1), tile);
         }
     }
 
