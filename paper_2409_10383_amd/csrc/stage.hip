@@ -71,6 +71,15 @@ __device__ __forceinline__ void wait_vmem()
     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt unconstrained
 }
 
+// workgroup barrier over this wave's LDS reads and writes only: the next
+// field's copy (counted as vector memory) stays in flight across it.  A
+// fence would also wait for that copy, since it targets LDS; the memory
+// clobber keeps the compiler from moving memory accesses across.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // one axis of a staged field: centred d1, d2 (both optional) and the
 // advection + dissipation contribution; no 1/h factors
 // va is the advection speed along the axis (0 when advection is off) and
@@ -134,7 +143,7 @@ __global__ __launch_bounds__(256) void k_stage(const StageArgs a)
         const int w = x * per + k;
         if (w >= a.nwork) break;
         stage_tile<N, T, C, TX, TY, TZ>(a, a.work[w], tile, dxs, dys, adks);
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -295,7 +304,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
             // conformal metric: first derivatives, Ricci second-derivative term
             const int p = sl;
             first_pass();
-            __syncthreads();
+            lds_barrier();
             C d1[3], d2[3], mxy, mxz, myz;
             sweep(F_GXX + p, false, d1, d2, T1(), T1());
             mixed(mxy, mxz, myz);
@@ -313,7 +322,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
         } else if (sl < 8) {
             // chi and alpha: first and second derivatives
             first_pass();
-            __syncthreads();
+            lds_barrier();
             C d1[3], d2[3], mxy, mxz, myz;
             const bool is_chi = sl == 6;
             sweep(is_chi ? F_CHI : F_ALPHA, !is_chi, d1, d2, T1(), T1());
@@ -327,7 +336,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
             // shift: first derivatives, g~^jk d_j d_k beta^i and d_j d_k beta^k
             const int q = sl - 8;
             first_pass();
-            __syncthreads();
+            lds_barrier();
             C d1[3], d2[3], mxy, mxz, myz;
             sweep(F_BETAX + q, true, d1, d2, T1(), T1());
             mixed(mxy, mxz, myz);
@@ -383,7 +392,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
             put_adk(F_AXX + (sl - 16), ad * ih);
         }
         if (NBUF == 1 && sl + 1 < NF) {
-            __syncthreads();   // every wave is done with the single buffer
+            lds_barrier();     // every wave is done with the single buffer
             issue(field_of(sl + 1), tile);
         }
     }
