@@ -243,6 +243,40 @@ int z4c_constraints(struct z4c_pack *pack, int32_t reg, void *per_zone_out,
 int z4c_refine_flags(struct z4c_pack *pack, int32_t reg, const z4c_refine_params *rp,
                      int8_t *flags_out, void *stream);
 
+/* ------------------------------------------------------------- regrid */
+
+/* Regrid plan (Sec. 3.3: the refinement criteria drive the mesh; the 2:1
+ * rule between neighbouring MeshBlocks).  flags (host, one per block of
+ * `pack`, as z4c_refine_flags writes them): +1 refine, -1 derefine, 0 keep.
+ * A refined block becomes its eight children (same n, level + 1, corners
+ * 2*ilo + n*{0,1}^3), unless it is already at level_max.  Eight leaves
+ * flagged -1 that are the aligned children of one parent (same level >= 1
+ * and n, ilo = 2*P.ilo + n*{0,1}^3) merge into that parent.  Blocks within
+ * reach of each other's ghost stencils (2g cells of the finer one,
+ * periodic images included) end at most one level apart: refinement
+ * spreads to coarser neighbours, merges that would break the rule are
+ * cancelled.  Writes the new blocks (host) in the old order, children in
+ * place of their parent (z, y, x order), a merged parent in place of its
+ * first child.  *out_n receives the count; Z4C_ENOMEM (nothing written
+ * past out_cap) if it exceeds out_cap.  Host only, no stream. */
+int z4c_regrid_plan(const struct z4c_pack *pack, const int8_t *flags, int32_t level_max,
+                    z4c_block *out_blocks, int32_t out_cap, int32_t *out_n);
+
+/* Regrid transfer (Sec. 3.1, Eqs. 1-2): fills the active cells of state
+ * register dst_reg of `dst` (a bound pack of the same parameters whose
+ * blocks come from z4c_regrid_plan on `src`'s blocks) from state register
+ * src_reg of `src`: a block present in both is copied; a block one level
+ * finer than the src block containing it is prolongated from that block
+ * (np = g+1 coarse centres nearest each fine centre per axis, the operator
+ * of the fine ghost fill, reading the src block's ghosts); a block whose
+ * eight children (same n) are src blocks is restricted from them (np fine
+ * centres inside the owning child, the window of the coarse ghost fill).
+ * Fills the ghosts of src_reg first (src's ghost cells are written).
+ * Ghosts of dst_reg are left to the next fill.  Z4C_EINVAL if a dst block
+ * is none of the three.  Enqueued on `stream`. */
+int z4c_regrid_transfer(struct z4c_pack *src, int32_t src_reg, struct z4c_pack *dst, int32_t dst_reg,
+                        void *stream);
+
 /* ----------------------------------------------- learned refinement */
 /* The learned indicator predicts, per MeshBlock, the truncation error the
  * chi-based criteria of Sec. 3.3 stand in for, from cheap block features;

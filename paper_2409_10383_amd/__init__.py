@@ -70,7 +70,8 @@ EXPORTS = ["z4c_pack_create", "z4c_pack_query", "z4c_block_offset", "z4c_pack_bi
            "z4c_rk4_step", "z4c_constraints", "z4c_refine_flags", "z4c_stencil_weights",
            "z4c_profile", "z4c_profile_read", "z4c_features", "z4c_pack_inject_2h", "z4c_labels",
            "z4c_feature_stats", "z4c_mlp_normalize", "z4c_mlp_forward", "z4c_mlp_backward",
-           "z4c_mlp_adam", "z4c_refine_flags_learned", "z4c_set_variant", "z4c_autotune"]
+           "z4c_mlp_adam", "z4c_refine_flags_learned", "z4c_set_variant", "z4c_autotune",
+           "z4c_regrid_plan", "z4c_regrid_transfer"]
 MLP_NPARAM = 5313
 
 
@@ -123,6 +124,9 @@ def lib():
                                                C.POINTER(C.c_int8), C.POINTER(C.c_int8), vp]
         L.z4c_set_variant.argtypes = [vp, C.c_int32, C.c_int32, vp]
         L.z4c_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32), vp]
+        L.z4c_regrid_plan.argtypes = [vp, C.POINTER(C.c_int8), C.c_int32, C.POINTER(Block), C.c_int32,
+                                      C.POINTER(C.c_int32)]
+        L.z4c_regrid_transfer.argtypes = [vp, C.c_int32, vp, C.c_int32, vp]
         L.z4c_profile.argtypes = [vp, C.c_int32]
         L.z4c_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.c_int32]
         _lib = L
@@ -310,6 +314,19 @@ class Pack:
         self._check(lib().z4c_autotune(self.h, reps, t, C.byref(ch), _stream_ptr(stream)))
         return int(ch.value), np.array(t[:])
 
+    def regrid_plan(self, flags, level_max: int):
+        """The mesh z4c_regrid_plan makes from per-block flags (+1 refine,
+        -1 derefine, 0 keep): a z4c_inputs.Mesh on the same domain."""
+        return _plan(self.h, self.mesh, flags, level_max)
+
+    def regrid(self, flags, level_max: int, reg: int = REG_U, stream=None) -> "Pack":
+        """A new pack on the regridded mesh whose U holds register `reg` of
+        this one, carried over by z4c_regrid_transfer (fills this pack's
+        ghosts of `reg` first)."""
+        new = Pack(self.regrid_plan(flags, level_max), self.params, self.precision)
+        self._check(lib().z4c_regrid_transfer(self.h, reg, new.h, REG_U, _stream_ptr(stream)))
+        return new
+
     def profile(self, enable: bool = True):
         self._check(lib().z4c_profile(self.h, 1 if enable else 0))
 
@@ -357,6 +374,42 @@ class Pack:
         flags = (C.c_int8 * self.mesh.nb)()
         self._check(lib().z4c_refine_flags(self.h, reg, C.byref(rp), flags, _stream_ptr(stream)))
         return np.array(flags[:], dtype=np.int8)
+
+
+# ---------------------------------------------------------------- regrid
+def _plan(h, mesh, flags, level_max):
+    import dataclasses
+    f = np.ascontiguousarray(flags, dtype=np.int8)
+    if f.shape != (mesh.nb,):
+        raise ValueError("one flag per block")
+    fp = f.ctypes.data_as(C.POINTER(C.c_int8))
+    n = C.c_int32()
+    rc = lib().z4c_regrid_plan(h, fp, level_max, None, 0, C.byref(n))
+    if rc not in (0, -2):
+        raise Z4cError(rc, "z4c_regrid_plan rejected its arguments")
+    out = (Block * max(n.value, 1))()
+    rc = lib().z4c_regrid_plan(h, fp, level_max, out, n.value, C.byref(n))
+    if rc:
+        raise Z4cError(rc, "z4c_regrid_plan")
+    nb = n.value
+    return dataclasses.replace(
+        mesh,
+        level=np.array([out[b].level for b in range(nb)], dtype=np.int32),
+        n=np.array([out[b].n for b in range(nb)], dtype=np.int32),
+        ilo=np.array([list(out[b].ilo) for b in range(nb)], dtype=np.int32).reshape(nb, 3))
+
+
+def regrid_plan(mesh, params: dict, flags, level_max: int):
+    """z4c_regrid_plan on a host-only pack of `mesh` (no device memory)."""
+    P = make_params(mesh, params)
+    h = C.c_void_p()
+    rc = lib().z4c_pack_create(C.byref(P), make_blocks(mesh), mesh.nb, C.byref(h))
+    if rc:
+        raise Z4cError(rc, "z4c_pack_create rejected the pack description")
+    try:
+        return _plan(h, mesh, flags, level_max)
+    finally:
+        lib().z4c_pack_destroy(h)
 
 
 # ---------------------------------------------------------------- learned part

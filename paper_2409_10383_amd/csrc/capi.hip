@@ -14,61 +14,10 @@
 #include <string>
 #include <vector>
 
-#include "../../include/z4c.h"
-#include "kernels.hpp"
+#include "pack.hpp"
 #include "stencils.hpp"
 
-using namespace z4c;
-
-struct z4c_pack {
-    z4c_params p;
-    std::vector<z4c_block> blk;
-    std::vector<BlockDev> bdev;
-    std::vector<WorkItem> work;
-    std::vector<int32_t> map;
-    LookupDev L;
-    bool multilevel = false;
-    // cross-level fill tables
-    std::vector<XferItem> xfer;
-    std::vector<ProlongItem> prol;
-    std::vector<ProlongGroup> pgrp;
-    std::vector<ImageSlice> islice;
-    std::vector<int64_t> img_off;     // per block: offset of its coarse image, -1 if none
-    std::vector<int32_t> img_fstride;
-    int64_t image_elems = 0;
-    std::vector<double> rw, pw, wtab;
-    int64_t shadow_elems = 0;
-    size_t ws_xfer = 0, ws_prol = 0, ws_pgrp = 0, ws_islice = 0, ws_w = 0, ws_shadow = 0, ws_image = 0;
-    size_t ws_first = 0, ws_feat = 0, ws_x = 0, ws_y = 0;
-    std::vector<int32_t> first_work;
-    int maxghost = 0;
-    int64_t zones = 0;
-    size_t reg_bytes[Z4C_NREG] = {0, 0, 0, 0};
-    // workspace carve-up (byte offsets)
-    size_t ws_blocks = 0, ws_work = 0, ws_map = 0, ws_part = 0, ws_total = 0;
-    // bound memory
-    bool bound = false;
-    void* reg[Z4C_NREG] = {nullptr, nullptr, nullptr, nullptr};
-    char* ws = nullptr;
-    std::vector<double> part_host;
-    std::string err;
-    // stage-kernel variant (tile shape) and launch mode
-    int variant = 0;
-    bool persistent = false;
-    int grid_persistent = 0;
-    // captured RK4 step (hipGraph), valid for one (dt, stream)
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    double graph_dt = 0.0;
-    hipStream_t graph_stream = nullptr;
-    // optional kernel timing
-    bool prof = false;
-    struct EvPair { hipEvent_t a, b; int kind; };
-    std::vector<EvPair> ev;
-    double prof_acc[6] = {0, 0, 0, 0, 0, 0};
-};
-
-namespace {
+namespace z4c_host {
 
 int fail(z4c_pack* pk, int code, const char* fmt, ...)
 {
@@ -82,6 +31,27 @@ int fail(z4c_pack* pk, int code, const char* fmt, ...)
     }
     return code;
 }
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// Lagrange weights (Eq. 1 of the paper) of the nodes q + 1/2, q = 0..n-1, at t
+void lagrange_half(int n, double t, double* w)
+{
+    for (int q = 0; q < n; ++q) {
+        double p = 1.0;
+        for (int m = 0; m < n; ++m)
+            if (m != q) p *= (t - (m + 0.5)) / ((q + 0.5) - (m + 0.5));
+        w[q] = p;
+    }
+}
+
+}  // namespace z4c_host
+
+using namespace z4c_host;
+
+namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -127,21 +97,6 @@ bool build_work(const std::vector<z4c_block>& blk, int v, std::vector<WorkItem>&
                 }
     }
     return true;
-}
-
-hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
-
-int64_t fdiv(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
-
-// Lagrange weights (Eq. 1 of the paper) of the nodes q + 1/2, q = 0..n-1, at t
-void lagrange_half(int n, double t, double* w)
-{
-    for (int q = 0; q < n; ++q) {
-        double p = 1.0;
-        for (int m = 0; m < n; ++m)
-            if (m != q) p *= (t - (m + 0.5)) / ((q + 0.5) - (m + 0.5));
-        w[q] = p;
-    }
 }
 
 // Host-side queries on the block layout of a pack.
@@ -239,7 +194,7 @@ int build_xlevel(z4c_pack* pk)
         // shadow box of this block at level l-1 (allocated on first use)
         int64_t S0[3];
         const int64_t SE = (n + 2 * g) / 2 + 2 * (np + 1) + 2;
-        for (int a = 0; a < 3; ++a) S0[a] = fdiv(B.ilo[a] - g, 2) - (np + 1);
+        for (int a = 0; a < 3; ++a) S0[a] = floor_div(B.ilo[a] - g, 2) - (np + 1);
         int64_t shoff = -1;
         std::vector<uint8_t> mark;
         std::unordered_map<int64_t, size_t> pgmap;  // parent's child-(0,0,0) cell -> group
@@ -275,7 +230,7 @@ int build_xlevel(z4c_pack* pk)
                     int64_t s[3];
                     int parity = 0;
                     for (int a = 0; a < 3; ++a) {
-                        const int64_t J = fdiv(Iu[a], 2);
+                        const int64_t J = floor_div(Iu[a], 2);
                         const int odd = (int)(Iu[a] - 2 * J);
                         parity |= odd << a;
                         s[a] = (np % 2) ? J - (np - 1) / 2 : (odd ? J - np / 2 + 1 : J - np / 2);
@@ -564,6 +519,7 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
     pk->ws_shadow = o; o = align256(o + esz * (size_t)pk->shadow_elems);
     pk->ws_islice = o; o = align256(o + sizeof(ImageSlice) * pk->islice.size());
     pk->ws_image = o;  o = align256(o + esz * (size_t)pk->image_elems);
+    pk->ws_regrid = o; o = align256(o + sizeof(RegridDesc) * nblocks);
     pk->ws_total = o;
     pk->part_host.resize(16 * pk->work.size());
     pk->first_work.assign(nblocks + 1, 0);

@@ -79,21 +79,6 @@ __global__ __launch_bounds__(256) void k_fill_same(const FillArgs a)
     for (int f = 0; f < NF; ++f) r[d + f * B.slab] = r[so + f * SB.slab];
 }
 
-// Restriction window of coarse cell kc (0 <= kc < n/2) inside a fine block
-// of n active cells per axis: first fine cell o of the np-point window and
-// the weight set d (evaluation point at the fine face o + d).  Centred where
-// it fits; for odd np the extra point goes towards the block's interior;
-// clamped to the block's active cells.
-__device__ __forceinline__ void rwin(int kc, int n, int np, int& o, int& d)
-{
-    const int c = 2 * kc;
-    int st = (np % 2 == 0) ? c - np / 2 + 1 : ((2 * kc + 1 < n / 2) ? c - (np - 1) / 2 + 1 : c - (np - 1) / 2);
-    st = st < 0 ? 0 : st;
-    st = st + np > n ? n - np : st;
-    o = st;
-    d = c + 1 - st;
-}
-
 // Coarse image of a fine block: separable x, y, z passes through LDS (the
 // same association order as a direct triple sum: x innermost).
 template <class T, int NP>

@@ -34,6 +34,21 @@ struct FillArgs {
     int32_t maxghost;         // ghost cells of the largest block
 };
 
+// Restriction window of coarse cell kc (0 <= kc < n/2) inside a fine block
+// of n active cells per axis: first fine cell o of the np-point window and
+// the weight set d (evaluation point at the fine face o + d).  Centred where
+// it fits; for odd np the extra point goes towards the block's interior;
+// clamped to the block's active cells.
+__device__ __forceinline__ void rwin(int kc, int n, int np, int& o, int& d)
+{
+    const int c = 2 * kc;
+    int st = (np % 2 == 0) ? c - np / 2 + 1 : ((2 * kc + 1 < n / 2) ? c - (np - 1) / 2 + 1 : c - (np - 1) / 2);
+    st = st < 0 ? 0 : st;
+    st = st + np > n ? n - np : st;
+    o = st;
+    d = c + 1 - st;
+}
+
 // LDS budget of the image restriction (doubles): x-pass and y-pass partials
 constexpr int RI_XMAX = 4096, RI_YMAX = 1536;
 
@@ -50,6 +65,19 @@ struct XlevelArgs {
     const double* pw;         // prolongation weights [2][8]: parity, point q
     int64_t nxfer, nprol, npgrp, nislice;
     int32_t npts;             // g + 1
+};
+
+// Regrid transfer: active cells of the destination pack's register from
+// the source pack's (ghost-filled) register
+struct RegridArgs {
+    const void* src;          // source register
+    void* dst;                // destination register
+    const BlockDev* sblocks;  // source block table
+    const BlockDev* dblocks;  // destination block table
+    const RegridDesc* desc;   // per destination block
+    int32_t g, npts;
+    double rw[64];            // restriction weights [set d][point]
+    double pw[16];            // prolongation weights [parity][point]
 };
 
 struct DiagArgs {
@@ -110,5 +138,6 @@ int stage_occupancy(int N, int prec, int variant);
 hipError_t launch_fill(int prec, const FillArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_diag(int N, int prec, const DiagArgs& a, int nwork, hipStream_t s);
 hipError_t launch_xlevel(int prec, const XlevelArgs& a, hipStream_t s);
+hipError_t launch_regrid(int prec, const RegridArgs& a, int nblocks, int maxn, hipStream_t s);
 
 }  // namespace z4c

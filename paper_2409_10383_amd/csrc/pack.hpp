@@ -1,0 +1,75 @@
+// Host-side state of a MeshBlockPack (struct z4c_pack of the C ABI) and the
+// helpers the host runtime's translation units share.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/z4c.h"
+#include "kernels.hpp"
+
+using namespace z4c;
+
+struct z4c_pack {
+    z4c_params p;
+    std::vector<z4c_block> blk;
+    std::vector<BlockDev> bdev;
+    std::vector<WorkItem> work;
+    std::vector<int32_t> map;
+    LookupDev L;
+    bool multilevel = false;
+    // cross-level fill tables
+    std::vector<XferItem> xfer;
+    std::vector<ProlongItem> prol;
+    std::vector<ProlongGroup> pgrp;
+    std::vector<ImageSlice> islice;
+    std::vector<RegridDesc> regrid_desc;  // last regrid into this pack (kept for the upload)
+    std::vector<int64_t> img_off;     // per block: offset of its coarse image, -1 if none
+    std::vector<int32_t> img_fstride;
+    int64_t image_elems = 0;
+    std::vector<double> rw, pw, wtab;
+    int64_t shadow_elems = 0;
+    size_t ws_xfer = 0, ws_prol = 0, ws_pgrp = 0, ws_islice = 0, ws_w = 0, ws_shadow = 0, ws_image = 0;
+    size_t ws_regrid = 0;
+    size_t ws_first = 0, ws_feat = 0, ws_x = 0, ws_y = 0;
+    std::vector<int32_t> first_work;
+    int maxghost = 0;
+    int64_t zones = 0;
+    size_t reg_bytes[Z4C_NREG] = {0, 0, 0, 0};
+    // workspace carve-up (byte offsets)
+    size_t ws_blocks = 0, ws_work = 0, ws_map = 0, ws_part = 0, ws_total = 0;
+    // bound memory
+    bool bound = false;
+    void* reg[Z4C_NREG] = {nullptr, nullptr, nullptr, nullptr};
+    char* ws = nullptr;
+    std::vector<double> part_host;
+    std::string err;
+    // stage-kernel variant (tile shape) and launch mode
+    int variant = 0;
+    bool persistent = false;
+    int grid_persistent = 0;
+    // captured RK4 step (hipGraph), valid for one (dt, stream)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    double graph_dt = 0.0;
+    hipStream_t graph_stream = nullptr;
+    // optional kernel timing
+    bool prof = false;
+    struct EvPair { hipEvent_t a, b; int kind; };
+    std::vector<EvPair> ev;
+    double prof_acc[6] = {0, 0, 0, 0, 0, 0};
+};
+
+namespace z4c_host {
+
+// record a message on the pack and return `code`
+int fail(z4c_pack* pk, int code, const char* fmt, ...);
+hipStream_t as_stream(void* s);
+// floor division
+int64_t floor_div(int64_t a, int64_t b);
+// Lagrange weights of the nodes q + 1/2, q = 0..n-1, at t
+void lagrange_half(int n, double t, double* w);
+
+}  // namespace z4c_host

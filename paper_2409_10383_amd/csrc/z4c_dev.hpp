@@ -90,6 +90,16 @@ struct ProlongGroup {
     int32_t fstride;      // field stride of the shadow box (elements)
 };
 
+// How a block of a regridded pack gets its active data from the old pack:
+// kind 0 copy of block src[0] (same geometry), 1 prolongation from the
+// coarser block src[0] that contains it, 2 restriction from its eight
+// children src[cz*4 + cy*2 + cx] (same cell count).
+struct RegridDesc {
+    int32_t kind;
+    int32_t src[8];
+    int32_t pad;
+};
+
 // physics / method parameters as the kernels read them
 struct ParamsDev {
     double ko_sigma, kappa1, kappa2, eta, mu_S, chi_floor, alpha_floor;
