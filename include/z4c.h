@@ -196,7 +196,11 @@ int z4c_fill_ghosts(struct z4c_pack *pack, int32_t reg, void *stream);
 int z4c_rhs(struct z4c_pack *pack, int32_t src_reg, void *rhs_out, void *stream);
 
 /* One classic RK4 stage (stage = 1..4), fused with the RHS and, unless the
- * boundary condition is USER, preceded by the ghost fill of the stage input:
+ * boundary condition is USER, preceded by the ghost fill of the stage input
+ * (where a block's neighbour region in some direction is one block of the
+ * same level and size, the stage reads that neighbour's active cells
+ * directly and those ghost cells are not written; z4c_fill_ghosts always
+ * writes every ghost cell):
  *   1: k1=F(U):  S1 = U + dt/2 k1, A  = U + dt/6 k1
  *   2: k2=F(S1): S2 = U + dt/2 k2, A += dt/3 k2
  *   3: k3=F(S2): S1 = U + dt k3,   A += dt/3 k3

@@ -10,6 +10,8 @@
 #include <cstring>
 #include <new>
 #include <type_traits>
+#include <map>
+#include <tuple>
 #include <unordered_map>
 #include <string>
 #include <vector>
@@ -340,6 +342,63 @@ int build_xlevel(z4c_pack* pk)
     return Z4C_OK;
 }
 
+// Virtual halos: the stage kernel's staged tiles read a same-level neighbour's
+// active cells directly where the neighbour region of direction (dx, dy, dz)
+// is one block of the same level and size (periodic wrap included), so the
+// stage path's ghost fill leaves those ghost cells alone.  vnbr[27 b + idx]
+// is the element offset that puts the ghosted index of block b's frame onto
+// the neighbour's cells (the block's own offset where the ghosts are real).
+// FP64 tiles are copied in 16-byte lanes, which must neither straddle a
+// block face nor lose alignment: that needs an even ghost depth and halo.
+void build_virtual_halos(z4c_pack* pk)
+{
+    const int nb = (int)pk->blk.size();
+    const int g = pk->p.nghost, R = pk->p.fd_order / 2 + 1;
+    pk->vnbr.assign((size_t)27 * nb, 0);
+    pk->vmask.assign(nb, 0u);
+    for (int b = 0; b < nb; ++b)
+        for (int i = 0; i < 27; ++i) pk->vnbr[27 * b + i] = pk->bdev[b].off;
+    const bool fp64 = pk->p.precision == Z4C_FP64;
+    if (pk->p.bc == Z4C_BC_USER) return;
+    if (fp64 && ((g & 1) || (R & 1))) return;
+    std::map<std::tuple<int, int, int64_t, int64_t, int64_t>, int> at;   // (level, n, ilo) -> block
+    for (int b = 0; b < nb; ++b) {
+        const z4c_block& B = pk->blk[b];
+        at[std::make_tuple(B.level, B.n, (int64_t)B.ilo[0], (int64_t)B.ilo[1], (int64_t)B.ilo[2])] = b;
+    }
+    for (int b = 0; b < nb; ++b) {
+        const z4c_block& B = pk->blk[b];
+        const BlockDev& D = pk->bdev[b];
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (!dx && !dy && !dz) continue;
+                    const int dd[3] = {dx, dy, dz};
+                    int64_t J[3];
+                    bool inside = true;
+                    for (int a = 0; a < 3; ++a) {
+                        const int64_t N = (int64_t)pk->p.nroot[a] << B.level;
+                        J[a] = (int64_t)B.ilo[a] + (int64_t)dd[a] * B.n;
+                        if (J[a] < 0 || J[a] >= N) {
+                            if (pk->p.bc != Z4C_BC_PERIODIC) inside = false;
+                            J[a] = ((J[a] % N) + N) % N;
+                        }
+                    }
+                    if (!inside) continue;
+                    auto it = at.find(std::make_tuple(B.level, B.n, J[0], J[1], J[2]));
+                    if (it == at.end()) continue;
+                    const BlockDev& T = pk->bdev[it->second];
+                    const int64_t E = D.E;
+                    const int64_t v = T.off - (int64_t)B.n * (dz * E * E + dy * E + dx);
+                    // element offsets of the staged cells stay within int32
+                    if (std::llabs(v - D.off) > ((int64_t)1 << 30)) continue;
+                    const int idx = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+                    pk->vnbr[27 * b + idx] = v;
+                    pk->vmask[b] |= 1u << idx;
+                }
+    }
+}
+
 // bracket a launch with events when profiling is on (kind 0 stage, 1 fill)
 struct ProfScope {
     z4c_pack* pk;
@@ -501,6 +560,7 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
         const int rc = build_xlevel(pk);
         if (rc) { delete pk; return rc; }
     }
+    build_virtual_halos(pk);
 
     // workspace
     size_t o = 0;
@@ -520,6 +580,8 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
     pk->ws_islice = o; o = align256(o + sizeof(ImageSlice) * pk->islice.size());
     pk->ws_image = o;  o = align256(o + esz * (size_t)pk->image_elems);
     pk->ws_regrid = o; o = align256(o + sizeof(RegridDesc) * nblocks);
+    pk->ws_vnbr = o;   o = align256(o + sizeof(int64_t) * 27 * nblocks);
+    pk->ws_vmask = o;  o = align256(o + sizeof(uint32_t) * nblocks);
     pk->ws_total = o;
     pk->part_host.resize(16 * pk->work.size());
     pk->first_work.assign(nblocks + 1, 0);
@@ -581,6 +643,12 @@ int z4c_pack_bind(z4c_pack* pk, void* const regs[Z4C_NREG], void* workspace, siz
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !pk->prol.empty())
         e = hipMemcpyAsync(ws + pk->ws_prol, pk->prol.data(), sizeof(ProlongItem) * pk->prol.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + pk->ws_vnbr, pk->vnbr.data(), sizeof(int64_t) * pk->vnbr.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + pk->ws_vmask, pk->vmask.data(), sizeof(uint32_t) * pk->vmask.size(),
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !pk->islice.empty())
         e = hipMemcpyAsync(ws + pk->ws_islice, pk->islice.data(), sizeof(ImageSlice) * pk->islice.size(),
@@ -644,13 +712,13 @@ int z4c_profile_read(z4c_pack* pk, double* out, int32_t reset)
 
 const char* z4c_last_error(const z4c_pack* pk) { return pk ? pk->err.c_str() : "null pack"; }
 
-int z4c_fill_ghosts(z4c_pack* pk, int32_t reg, void* stream)
+// ghost fill; `virt` leaves the ghost cells of virtual-halo directions
+// (read directly from neighbours by the stage kernel) unwritten
+static int fill_impl(z4c_pack* pk, int32_t reg, void* stream, bool virt)
 {
-    if (!pk) return Z4C_EINVAL;
-    if (reg < Z4C_REG_U || reg > Z4C_REG_S2) return fail(pk, Z4C_EINVAL, "bad register %d", reg);
-    if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
     if (pk->p.bc == Z4C_BC_USER) return Z4C_OK;
     FillArgs a;
+    a.skip = virt ? reinterpret_cast<const uint32_t*>(pk->ws + pk->ws_vmask) : nullptr;
     a.reg = pk->reg[reg];
     a.blocks = reinterpret_cast<const BlockDev*>(pk->ws + pk->ws_blocks);
     a.map = reinterpret_cast<const int32_t*>(pk->ws + pk->ws_map);
@@ -684,6 +752,14 @@ int z4c_fill_ghosts(z4c_pack* pk, int32_t reg, void* stream)
     return Z4C_OK;
 }
 
+int z4c_fill_ghosts(z4c_pack* pk, int32_t reg, void* stream)
+{
+    if (!pk) return Z4C_EINVAL;
+    if (reg < Z4C_REG_U || reg > Z4C_REG_S2) return fail(pk, Z4C_EINVAL, "bad register %d", reg);
+    if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
+    return fill_impl(pk, reg, stream, false);
+}
+
 static StageArgs stage_args(z4c_pack* pk)
 {
     StageArgs a;
@@ -696,6 +772,7 @@ static StageArgs stage_args(z4c_pack* pk)
     a.g = pk->p.nghost;
     a.A = static_cast<double*>(pk->reg[Z4C_REG_A]);
     a.U = pk->reg[Z4C_REG_U];
+    a.vnbr = reinterpret_cast<const int64_t*>(pk->ws + pk->ws_vnbr);
     return a;
 }
 
@@ -723,7 +800,7 @@ int z4c_rk4_stage(z4c_pack* pk, int32_t stage, double dt, void* stream)
     if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
     static const int src_of[5] = {0, Z4C_REG_U, Z4C_REG_S1, Z4C_REG_S2, Z4C_REG_S1};
     static const int dst_of[5] = {0, Z4C_REG_S1, Z4C_REG_S2, Z4C_REG_S1, Z4C_REG_U};
-    int rc = z4c_fill_ghosts(pk, src_of[stage], stream);
+    int rc = fill_impl(pk, src_of[stage], stream, true);
     if (rc) return rc;
     StageArgs a = stage_args(pk);
     a.src = pk->reg[src_of[stage]];

@@ -57,6 +57,11 @@ __global__ __launch_bounds__(256) void k_fill_same(const FillArgs a)
     int i, j, k;
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (!ghost_cell(q, n, g, E, i, j, k)) return;
+    if (a.skip) {
+        const int dx = i < g ? 0 : (i >= g + n ? 2 : 1), dy = j < g ? 0 : (j >= g + n ? 2 : 1),
+                  dz = k < g ? 0 : (k >= g + n ? 2 : 1);
+        if ((a.skip[b] >> ((dz * 3 + dy) * 3 + dx)) & 1u) return;
+    }
     int64_t G[3] = {(int64_t)B.ilo[0] + i - g, (int64_t)B.ilo[1] + j - g, (int64_t)B.ilo[2] + k - g};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {

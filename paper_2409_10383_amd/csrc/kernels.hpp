@@ -13,6 +13,7 @@ struct StageArgs {
     double* rhs_out;          // z4c_rhs only (interior layout)
     const BlockDev* blocks;
     const WorkItem* work;
+    const int64_t* vnbr;      // per block, 27 direction offsets of the staged halo
     ParamsDev P;
     double dt;
     int32_t stage;            // 1..4, 0 = RHS only
@@ -32,6 +33,7 @@ struct FillArgs {
     int32_t g, bc;
     int32_t nroot[3];
     int32_t maxghost;         // ghost cells of the largest block
+    const uint32_t* skip;     // per block, directions left alone (virtual halos); null = none
 };
 
 // Restriction window of coarse cell kc (0 <= kc < n/2) inside a fine block
@@ -86,6 +88,7 @@ struct DiagArgs {
     double* partial;          // [nwork][8]
     const BlockDev* blocks;
     const WorkItem* work;
+    const int64_t* vnbr;      // per block, 27 direction offsets of the staged halo
     ParamsDev P;
     double lo[3];
     int32_t ncentres;

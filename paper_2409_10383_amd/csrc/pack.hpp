@@ -32,7 +32,9 @@ struct z4c_pack {
     std::vector<double> rw, pw, wtab;
     int64_t shadow_elems = 0;
     size_t ws_xfer = 0, ws_prol = 0, ws_pgrp = 0, ws_islice = 0, ws_w = 0, ws_shadow = 0, ws_image = 0;
-    size_t ws_regrid = 0;
+    size_t ws_regrid = 0, ws_vnbr = 0, ws_vmask = 0;
+    std::vector<int64_t> vnbr;    // virtual halos: 27 offsets per block
+    std::vector<uint32_t> vmask;  // virtual-halo directions per block
     size_t ws_first = 0, ws_feat = 0, ws_x = 0, ws_y = 0;
     std::vector<int32_t> first_work;
     int maxghost = 0;

@@ -48,16 +48,16 @@ typedef __attribute__((address_space(3))) void* lptr_t;
 // Asynchronous copy of one staged field (global -> LDS, no registers): the
 // staged tile is dense in LDS (x fastest), so slot u of S bytes lands at
 // byte S*u; lane l of a wave writes S bytes at the wave's LDS base + S*l.
-// soff holds the byte offset (from the tile origin in the ghosted block) of
-// the first byte of each of this thread's slots.
-template <int S, int NSLOT, int NR>
+// soff holds the element offset (from the field's base in this block's
+// ghosted frame) of the first element of each of this thread's slots.
+template <int S, int ESZ, int NSLOT, int NR>
 __device__ __forceinline__ void dma_field(const char* gbase, char* lbase, const int (&soff)[NR])
 {
     const int t = threadIdx.x, w = t >> 6;
 #pragma unroll
     for (int r = 0; r < NR; ++r)
         if (r * 256 + t < NSLOT) {
-            const gptr_t src = (gptr_t)(gbase + soff[r]);
+            const gptr_t src = (gptr_t)(gbase + (int64_t)soff[r] * ESZ);
             const lptr_t dst = (lptr_t)(lbase + (r * 256 + w * 64) * S);
             if constexpr (S == 16) __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
             else __builtin_amdgcn_global_load_lds(src, dst, 4, 0, 0);
@@ -261,18 +261,25 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     // base and the tile's x origin are even when the ghost depth and the halo
     // differ by an even count; otherwise FP64 fields go as 4-byte halves
     const bool wide = sizeof(T) == 4 || ((g - R) & 1) == 0;
+    // staged cells outside the block read a same-level neighbour directly
+    // where the pack provides a virtual halo for that direction (the offset
+    // table then points the block's ghosted index at the neighbour's cells)
+    const int64_t* vn = a.vnbr + (int64_t)w.block * 27;
     int soff[NRS];
 #pragma unroll
     for (int r = 0; r < NRS; ++r) {
         const int q = (r * 256 + t) * (SLOT / (int)sizeof(T));   // first element of the slot
         const int x = q % SX, y = (q / SX) % SY, z = q / sxy;
-        soff[r] = ((z * E + y) * E + x) * (int)sizeof(T);
+        const int lx = x + w.i0 - R, ly = y + w.j0 - R, lz = z + w.k0 - R;
+        const int dir = ((lz < 0 ? 0 : (lz >= n ? 2 : 1)) * 3 + (ly < 0 ? 0 : (ly >= n ? 2 : 1))) * 3 +
+                        (lx < 0 ? 0 : (lx >= n ? 2 : 1));
+        soff[r] = (int)(vn[dir] - B.off) + ((lz + g) * E + (ly + g)) * E + (lx + g);
     }
     auto issue = [&](int f, C* buf) {
-        const char* gb = (const char*)(srcb + f * slab + base0);
         if (wide) {
-            dma_field<SLOT, NSLOT, NRS>(gb, (char*)buf, soff);
+            dma_field<SLOT, (int)sizeof(T), NSLOT, NRS>((const char*)(srcb + f * slab), (char*)buf, soff);
         } else {
+            const char* gb = (const char*)(srcb + f * slab + base0);
             constexpr int NS4 = G::NS * (int)sizeof(T) / 4, NR4 = (NS4 + 255) / 256;
             const int wv = t >> 6;
 #pragma unroll 4
