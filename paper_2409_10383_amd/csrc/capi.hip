@@ -348,19 +348,27 @@ int build_xlevel(z4c_pack* pk)
 // stage path's ghost fill leaves those ghost cells alone.  vnbr[27 b + idx]
 // is the element offset that puts the ghosted index of block b's frame onto
 // the neighbour's cells (the block's own offset where the ghosts are real).
-// FP64 tiles are copied in 16-byte lanes, which must neither straddle a
-// block face nor lose alignment: that needs an even ghost depth and halo.
+// FP64 tiles are copied in 16-byte lanes (two cells of an x row, even in
+// the ghosted frame), which must stay within one block's memory.  With an
+// even ghost depth no lane crosses a block face, and every direction can be
+// virtual.  With an odd one the lanes at the x faces straddle them, so only
+// directions with dx = 0 are virtual and a lane takes its direction from its
+// y and z alone: across the x face it reads that neighbour's own x ghosts,
+// which stay real.  Lanes that are not 16-byte aligned at all (ghost depth
+// and halo of different parity) copy per half cell from the block itself.
 void build_virtual_halos(z4c_pack* pk)
 {
     const int nb = (int)pk->blk.size();
     const int g = pk->p.nghost, R = pk->p.fd_order / 2 + 1;
     pk->vnbr.assign((size_t)27 * nb, 0);
     pk->vmask.assign(nb, 0u);
+    pk->virt_x = 1;
     for (int b = 0; b < nb; ++b)
         for (int i = 0; i < 27; ++i) pk->vnbr[27 * b + i] = pk->bdev[b].off;
     const bool fp64 = pk->p.precision == Z4C_FP64;
     if (pk->p.bc == Z4C_BC_USER) return;
-    if (fp64 && ((g & 1) || (R & 1))) return;
+    if (fp64 && ((g - R) & 1)) return;
+    if (fp64 && (g & 1)) pk->virt_x = 0;
     std::map<std::tuple<int, int, int64_t, int64_t, int64_t>, int> at;   // (level, n, ilo) -> block
     for (int b = 0; b < nb; ++b) {
         const z4c_block& B = pk->blk[b];
@@ -373,6 +381,7 @@ void build_virtual_halos(z4c_pack* pk)
             for (int dy = -1; dy <= 1; ++dy)
                 for (int dx = -1; dx <= 1; ++dx) {
                     if (!dx && !dy && !dz) continue;
+                    if (dx && !pk->virt_x) continue;
                     const int dd[3] = {dx, dy, dz};
                     int64_t J[3];
                     bool inside = true;
@@ -773,6 +782,7 @@ static StageArgs stage_args(z4c_pack* pk)
     a.A = static_cast<double*>(pk->reg[Z4C_REG_A]);
     a.U = pk->reg[Z4C_REG_U];
     a.vnbr = reinterpret_cast<const int64_t*>(pk->ws + pk->ws_vnbr);
+    a.virt_x = pk->virt_x;
     return a;
 }
 

@@ -20,6 +20,7 @@ struct StageArgs {
     int32_t g;
     int32_t nwork;            // work items
     int32_t persistent;       // 1: grid smaller than nwork, workgroups loop
+    int32_t virt_x;           // 0: a staged cell's halo direction ignores x
 };
 
 constexpr int NVARIANT = 4;

@@ -35,6 +35,7 @@ struct z4c_pack {
     size_t ws_regrid = 0, ws_vnbr = 0, ws_vmask = 0;
     std::vector<int64_t> vnbr;    // virtual halos: 27 offsets per block
     std::vector<uint32_t> vmask;  // virtual-halo directions per block
+    int virt_x = 1;               // 0: only directions with dx = 0 are virtual
     size_t ws_first = 0, ws_feat = 0, ws_x = 0, ws_y = 0;
     std::vector<int32_t> first_work;
     int maxghost = 0;

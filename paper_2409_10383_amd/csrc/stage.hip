@@ -272,7 +272,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
         const int x = q % SX, y = (q / SX) % SY, z = q / sxy;
         const int lx = x + w.i0 - R, ly = y + w.j0 - R, lz = z + w.k0 - R;
         const int dir = ((lz < 0 ? 0 : (lz >= n ? 2 : 1)) * 3 + (ly < 0 ? 0 : (ly >= n ? 2 : 1))) * 3 +
-                        (lx < 0 ? 0 : (lx >= n ? 2 : 1));
+                        (a.virt_x ? (lx < 0 ? 0 : (lx >= n ? 2 : 1)) : 1);
         soff[r] = (int)(vn[dir] - B.off) + ((lz + g) * E + (ly + g)) * E + (lx + g);
     }
     auto issue = [&](int f, C* buf) {
