@@ -53,6 +53,7 @@ def lib():
         L.or_refine_flags.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), dp, C.c_int,
                                       C.c_double, C.c_double, C.c_int, C.c_double, dp, C.c_int,
                                       C.POINTER(C.c_int8)]
+        L.or_psi4.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), dp, dp, dp]
         if hasattr(L, "or_block_features"):
             L.or_block_features.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), dp, dp]
         _lib = L
@@ -215,6 +216,20 @@ def constraints(om: OracleMesh, params: dict, u: np.ndarray, exclude=(), r_exc: 
 
 
 CRIT_CHI_MIN, CRIT_DCHI_MAX, CRIT_RADIUS = 0, 1, 2
+
+
+def psi4(om: OracleMesh, params: dict, u: np.ndarray, origin=(0.0, 0.0, 0.0), fill: bool = True):
+    """Per-block (2, n, n, n) Re/Im Psi4 in the coordinate tetrad about
+    `origin` (ghosts of u filled first unless fill is False)."""
+    if fill:
+        fill_ghosts(om, u)
+    nz = sum(int(n) ** 3 for n in om.mesh.n)
+    out = np.zeros(2 * nz)
+    o = np.ascontiguousarray(origin, dtype=np.float64)
+    rc = lib().or_psi4(C.byref(om.c), C.byref(make_params(params)), _dp(u), _dp(o), _dp(out))
+    if rc:
+        raise RuntimeError(f"oracle psi4 failed ({rc})")
+    return om.split_interior(out, 2)
 
 
 def block_features(om: OracleMesh, params: dict, u: np.ndarray, fill: bool = True) -> np.ndarray:

@@ -596,3 +596,195 @@ int or_refine_flags(const or_mesh *m, const or_params *p, const double *u, int c
     }
     return 0;
 }
+
+/* --------------------------------------------------------------- Psi4 */
+/* Outgoing Weyl scalar in a coordinate tetrad (Sec. 3.4 wave extraction).
+ * Physical metric gamma_ij = g~_ij / chi and extrinsic curvature
+ * K_ij = A~_ij / chi + gamma_ij K / 3 with K = Khat + 2 Theta; their
+ * derivatives follow from the centred derivatives of the evolved fields by
+ * the product rule.  Electric and magnetic parts of the Weyl tensor (vacuum):
+ *   E_ij = R_ij - K_ik K^k_j + K K_ij   (K the trace of K_ij),
+ *   B_ij = symmetric part of eps_i^kl D_k K_lj.
+ * Tetrad: radial v = x - origin, u = (-v_y, v_x, 0), w^a = eps^a_bc u^b v^c,
+ * Gram-Schmidt in the order v, w, u -> e_r, e_theta, e_phi;
+ * m = (e_theta + i e_phi)/sqrt 2 and Psi4 = -(E_ij - i B_ij) mbar^i mbar^j,
+ * which is  d2h+/dt2 - i d2hx/dt2  for an outgoing linear wave. */
+static int levi(int a, int b, int c)
+{
+    if (a == b || b == c || a == c) return 0;
+    return ((a == 0 && b == 1) || (a == 1 && b == 2) || (a == 2 && b == 0)) ? 1 : -1;
+}
+
+static void zone_psi4(const zone_t *z, const double x[3], double out[2])
+{
+    const double ic = 1.0 / z->chi;
+    double gam[3][3], dgam[3][3][3], ddgam[3][3][3][3], Kij[3][3], dKij[3][3][3], dK[3];
+    const double Kt = z->Khat + 2.0 * z->Theta;
+    for (int k = 0; k < 3; ++k) dK[k] = z->dKhat[k] + 2.0 * z->dTheta[k];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) gam[i][j] = z->g[i][j] * ic;
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) dgam[k][i][j] = (z->dg[k][i][j] - gam[i][j] * z->dchi[k]) * ic;
+    for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l)
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    ddgam[k][l][i][j] = (z->ddg[k][l][i][j] - dgam[k][i][j] * z->dchi[l] -
+                                         dgam[l][i][j] * z->dchi[k] - gam[i][j] * z->ddchi[k][l]) * ic;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Kij[i][j] = z->A[i][j] * ic + gam[i][j] * Kt / 3.0;
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                dKij[k][i][j] = (z->dA[k][i][j] - z->A[i][j] * z->dchi[k] * ic) * ic +
+                                dgam[k][i][j] * Kt / 3.0 + gam[i][j] * dK[k] / 3.0;
+    double gu[3][3], det;
+    inverse3(gam, gu, &det);
+    const double sg = sqrt(det);
+    /* Christoffel symbols Gamma^k_ij and their derivatives d_m Gamma^k_ij */
+    double G[3][3][3], dG[3][3][3][3], dgu[3][3][3];
+    for (int m = 0; m < 3; ++m)
+        for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l) {
+                double s = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) s -= gu[k][a] * gu[l][b] * dgam[m][a][b];
+                dgu[m][k][l] = s;
+            }
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double s = 0.0;
+                for (int l = 0; l < 3; ++l)
+                    s += gu[k][l] * (dgam[i][j][l] + dgam[j][i][l] - dgam[l][i][j]);
+                G[k][i][j] = 0.5 * s;
+            }
+    for (int m = 0; m < 3; ++m)
+        for (int k = 0; k < 3; ++k)
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    double s = 0.0;
+                    for (int l = 0; l < 3; ++l)
+                        s += dgu[m][k][l] * (dgam[i][j][l] + dgam[j][i][l] - dgam[l][i][j]) +
+                             gu[k][l] * (ddgam[m][i][j][l] + ddgam[m][j][i][l] - ddgam[m][l][i][j]);
+                    dG[m][k][i][j] = 0.5 * s;
+                }
+    /* Ricci tensor R_ij = d_k G^k_ij - d_j G^k_ik + G^k_kp G^p_ij - G^k_jp G^p_ik */
+    double R[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                s += dG[k][k][i][j] - dG[j][k][i][k];
+                for (int p = 0; p < 3; ++p) s += G[k][k][p] * G[p][i][j] - G[k][j][p] * G[p][i][k];
+            }
+            R[i][j] = s;
+        }
+    double trK = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) trK += gu[i][j] * Kij[i][j];
+    double E[3][3], Bm[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double kk = 0.0;
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) kk += Kij[i][k] * gu[k][l] * Kij[l][j];
+            E[i][j] = R[i][j] - kk + trK * Kij[i][j];
+        }
+    /* D_k K_lj */
+    double DK[3][3][3];
+    for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l)
+            for (int j = 0; j < 3; ++j) {
+                double s = dKij[k][l][j];
+                for (int m = 0; m < 3; ++m) s -= G[m][k][l] * Kij[m][j] + G[m][k][j] * Kij[l][m];
+                DK[k][l][j] = s;
+            }
+    double Braw[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0.0;
+            for (int m = 0; m < 3; ++m)
+                for (int k = 0; k < 3; ++k)
+                    for (int l = 0; l < 3; ++l) {
+                        const int e = levi(m, k, l);
+                        if (e) s += gam[i][m] * (e / sg) * DK[k][l][j];
+                    }
+            Braw[i][j] = s;
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Bm[i][j] = 0.5 * (Braw[i][j] + Braw[j][i]);
+    /* tetrad */
+    double v[3] = {x[0], x[1], x[2]}, u[3] = {-x[1], x[0], 0.0}, w[3];
+    for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (int d = 0; d < 3; ++d)
+            for (int b = 0; b < 3; ++b)
+                for (int c = 0; c < 3; ++c) {
+                    const int e = levi(d, b, c);
+                    if (e) s += gu[a][d] * (e * sg) * u[b] * v[c];
+                }
+        w[a] = s;
+    }
+#define DOT(p, q) (gam[0][0]*p[0]*q[0] + gam[1][1]*p[1]*q[1] + gam[2][2]*p[2]*q[2] + \
+                   gam[0][1]*(p[0]*q[1] + p[1]*q[0]) + gam[0][2]*(p[0]*q[2] + p[2]*q[0]) + \
+                   gam[1][2]*(p[1]*q[2] + p[2]*q[1]))
+    double uu = DOT(u, u), vv = DOT(v, v);
+    if (!(uu > 1e-24 * vv) || !(vv > 0.0)) { out[0] = out[1] = 0.0; return; }
+    double er[3], et[3], ep[3];
+    for (int a = 0; a < 3; ++a) er[a] = v[a] / sqrt(vv);
+    double wr = DOT(w, er);
+    for (int a = 0; a < 3; ++a) et[a] = w[a] - wr * er[a];
+    double tt = DOT(et, et);
+    for (int a = 0; a < 3; ++a) et[a] /= sqrt(tt);
+    double ur = DOT(u, er), ut = DOT(u, et);
+    for (int a = 0; a < 3; ++a) ep[a] = u[a] - ur * er[a] - ut * et[a];
+    double pp = DOT(ep, ep);
+    for (int a = 0; a < 3; ++a) ep[a] /= sqrt(pp);
+#undef DOT
+    double EP = 0.0, EQ = 0.0, BP = 0.0, BQ = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double P = 0.5 * (et[i] * et[j] - ep[i] * ep[j]);
+            const double Q = 0.5 * (et[i] * ep[j] + ep[i] * et[j]);
+            EP += E[i][j] * P; EQ += E[i][j] * Q;
+            BP += Bm[i][j] * P; BQ += Bm[i][j] * Q;
+        }
+    out[0] = -EP + BQ;
+    out[1] = EQ + BP;
+}
+
+int or_psi4(const or_mesh *m, const or_params *p, const double *u, const double *origin, double *out)
+{
+    stencils_t S;
+    if (make_stencils(p->fd_order, &S)) return -1;
+    int g = m->g;
+    if (g < S.N + 1) return -1;
+    int64_t roff = 0;
+    for (int b = 0; b < m->nb; ++b) {
+        int n = m->n[b];
+        blk_t B;
+        B.E = n + 2 * g;
+        B.u = u + or_block_offset(m, b);
+        B.sf = B.E * B.E * B.E;
+        B.st[0] = 1; B.st[1] = B.E; B.st[2] = B.E * B.E;
+        double h = m->dx0 / (double)(1 << m->level[b]), ih = 1.0 / h;
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    int64_t c = ((int64_t)(k + g) * B.E + (j + g)) * B.E + (i + g);
+                    zone_t z;
+                    load_zone(&B, &S, c, ih, &z, 1);
+                    double x[3] = {m->lo[0] + (m->ilo[3 * b] + i + 0.5) * h - origin[0],
+                                   m->lo[1] + (m->ilo[3 * b + 1] + j + 0.5) * h - origin[1],
+                                   m->lo[2] + (m->ilo[3 * b + 2] + k + 0.5) * h - origin[2]};
+                    double ps[2];
+                    zone_psi4(&z, x, ps);
+                    for (int q = 0; q < 2; ++q)
+                        out[roff + (((int64_t)q * n + k) * n + j) * n + i] = ps[q];
+                }
+        roff += (int64_t)2 * n * n * n;
+    }
+    return 0;
+}

@@ -90,6 +90,10 @@ int or_refine_flags(const or_mesh *m, const or_params *p, const double *u,
                     int level_max, double radius, const double *centre,
                     int radius_level, int8_t *flags);
 
+/* Psi4 (Re, Im) at every interior zone, coordinate tetrad about origin[3];
+ * u must have ghosts filled; out: interior layout with 2 components */
+int or_psi4(const or_mesh *m, const or_params *p, const double *u, const double *origin, double *out);
+
 /* 16 raw per-block features for the learned refinement indicator */
 int or_block_features(const or_mesh *m, const or_params *p, const double *u, double *feat);
 

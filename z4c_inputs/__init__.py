@@ -316,3 +316,44 @@ def workload(name: str):
         data = brill_lindquist(mesh, [(0.5, (5.0, 0.0, 0.0)), (0.5, (-5.0, 0.0, 0.0))])
         return mesh, params_default(6, eta=2.0), data, cfl * mesh.dx0, 1
     raise KeyError(name)
+
+
+# ------------------------------------------------------- geodesic spheres
+
+def geodesic_sphere(level: int, radius: float = 1.0, centre=(0.0, 0.0, 0.0)):
+    """Points (N, 3) and quadrature weights (N,) of a geodesic sphere: the
+    icosahedron with every triangle split into four `level` times, vertices
+    projected onto the sphere.  Each vertex carries a third of the solid
+    angle of every triangle it belongs to (weights sum to 4 pi)."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    V = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    V = [np.array(v, float) / np.linalg.norm(v) for v in V]
+    F = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5),
+         (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(level):
+        cache = {}
+
+        def mid(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in cache:
+                v = V[a] + V[b]
+                V.append(v / np.linalg.norm(v))
+                cache[key] = len(V) - 1
+            return cache[key]
+        G = []
+        for a, b, c in F:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            G += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        F = G
+    P = np.array(V)
+    w = np.zeros(len(P))
+    for a, b, c in F:
+        A, B, C = P[a], P[b], P[c]
+        # solid angle of the spherical triangle (Van Oosterom and Strackee)
+        num = abs(np.dot(A, np.cross(B, C)))
+        den = 1.0 + np.dot(A, B) + np.dot(B, C) + np.dot(C, A)
+        om = 2.0 * np.arctan2(num, den)
+        w[[a, b, c]] += om / 3.0
+    return P * radius + np.asarray(centre, float), w
