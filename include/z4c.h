@@ -57,6 +57,7 @@ extern "C" {
 #define Z4C_NREG 4
 #define Z4C_NNORM 6
 #define Z4C_NFEAT 16
+#define Z4C_MAXTRACK 8
 
 enum {
     Z4C_OK = 0,
@@ -280,6 +281,55 @@ int z4c_regrid_plan(const struct z4c_pack *pack, const int8_t *flags, int32_t le
  * is none of the three.  Enqueued on `stream`. */
 int z4c_regrid_transfer(struct z4c_pack *src, int32_t src_reg, struct z4c_pack *dst, int32_t dst_reg,
                         void *stream);
+
+/* ---------------------------------------- wave extraction, trackers */
+
+/* Outgoing Weyl scalar (Sec. 3.4 wave extraction) of state register `reg`
+ * at every active zone, in the coordinate tetrad about origin[3] (host):
+ * from the physical metric gamma_ij = g~_ij / chi and extrinsic curvature
+ * K_ij = A~_ij / chi + gamma_ij (Khat + 2 Theta)/3 (derivatives by the
+ * centred order-2N stencils and the product rule), E_ij = R_ij - K_ik K^k_j
+ * + K K_ij, B_ij = symmetric part of eps_i^kl D_k K_lj; tetrad vectors
+ * x - origin, eps(u, x - origin), u = (-y, x, 0) orthonormalised in that
+ * order (e_r, e_theta, e_phi), m = (e_theta + i e_phi)/sqrt 2; written is
+ * Psi4 = -(E_ij - i B_ij) mbar^i mbar^j (= d2h+/dt2 - i d2hx/dt2 for an
+ * outgoing linear wave).  0 where u vanishes (the tetrad's z axis).  out
+ * (device): interior layout, 2 components (Re, Im), double.  Fills the
+ * ghosts of `reg` first. */
+int z4c_psi4(struct z4c_pack *pack, int32_t reg, const double origin[3], void *out, void *stream);
+
+/* Cubic Lagrange interpolation (Sec. 3.4: quantities on extraction spheres,
+ * at punctures) of interior-layout double data with ncomp components per
+ * zone (device `src`, e.g. z4c_psi4's output) at npts points (device, x y z
+ * per point): each point takes the finest block whose active cells contain
+ * it and, per axis, the 4 cell centres nearest to it inside that block.
+ * out (device): npts x ncomp doubles, NaN for points outside the mesh. */
+int z4c_interp(struct z4c_pack *pack, const void *src, int32_t ncomp, const double *pts, int32_t npts,
+               double *out, void *stream);
+
+/* The same for fields first .. first+nfield-1 of state register `reg`
+ * (its active cells). */
+int z4c_interp_state(struct z4c_pack *pack, int32_t reg, int32_t first, int32_t nfield, const double *pts,
+                     int32_t npts, double *out, void *stream);
+
+/* Spin-weight -2 spherical-harmonic decomposition (Sec. 3.4) of complex
+ * values (device, Re Im per point) on a quadrature sphere: points (device,
+ * npts x 3) with weights (device) about centre[3] (host); for l = 2..lmax
+ * (lmax <= 12) and m = -l..l in that order,
+ * modes[2q], modes[2q+1] (device) = sum_p w_p v_p conj(-2Y_lm(theta_p, phi_p)),
+ * -2Y_22 = sqrt(5/(64 pi)) (1 + cos theta)^2 e^{2 i phi}. */
+int z4c_swsh_project(const double *values, const double *pts, const double *weights, int32_t npts,
+                     const double centre[3], int32_t lmax, double *modes, void *stream);
+
+/* Puncture trackers (Sec. 3.4): n <= Z4C_MAXTRACK positions (host) advected
+ * by dx/dt = -beta(x) with the classic RK4 of the evolution: every RK4 stage
+ * of z4c_rk4_stage / z4c_rk4_step first evaluates beta of that stage's input
+ * state at x + c_s dt k_(s-1) by z4c_interp_state's interpolation.  Setting
+ * replaces the punctures (n = 0 stops tracking) and drops a captured step
+ * graph.  Enqueued on `stream`. */
+int z4c_tracker_set(struct z4c_pack *pack, int32_t n, const double *pos, void *stream);
+/* Current positions (host, 3 per puncture).  Synchronises the stream. */
+int z4c_tracker_get(struct z4c_pack *pack, double *pos, void *stream);
 
 /* ----------------------------------------------- learned refinement */
 /* The learned indicator predicts, per MeshBlock, the truncation error the

@@ -71,7 +71,8 @@ EXPORTS = ["z4c_pack_create", "z4c_pack_query", "z4c_block_offset", "z4c_pack_bi
            "z4c_profile", "z4c_profile_read", "z4c_features", "z4c_pack_inject_2h", "z4c_labels",
            "z4c_feature_stats", "z4c_mlp_normalize", "z4c_mlp_forward", "z4c_mlp_backward",
            "z4c_mlp_adam", "z4c_refine_flags_learned", "z4c_set_variant", "z4c_autotune",
-           "z4c_regrid_plan", "z4c_regrid_transfer"]
+           "z4c_regrid_plan", "z4c_regrid_transfer", "z4c_psi4", "z4c_interp", "z4c_interp_state",
+           "z4c_swsh_project", "z4c_tracker_set", "z4c_tracker_get"]
 MLP_NPARAM = 5313
 
 
@@ -127,6 +128,13 @@ def lib():
         L.z4c_regrid_plan.argtypes = [vp, C.POINTER(C.c_int8), C.c_int32, C.POINTER(Block), C.c_int32,
                                       C.POINTER(C.c_int32)]
         L.z4c_regrid_transfer.argtypes = [vp, C.c_int32, vp, C.c_int32, vp]
+        dp = C.POINTER(C.c_double)
+        L.z4c_psi4.argtypes = [vp, C.c_int32, dp, vp, vp]
+        L.z4c_interp.argtypes = [vp, vp, C.c_int32, vp, C.c_int32, vp, vp]
+        L.z4c_interp_state.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, C.c_int32, vp, vp]
+        L.z4c_swsh_project.argtypes = [vp, vp, vp, C.c_int32, dp, C.c_int32, vp, vp]
+        L.z4c_tracker_set.argtypes = [vp, C.c_int32, dp, vp]
+        L.z4c_tracker_get.argtypes = [vp, dp, vp]
         L.z4c_profile.argtypes = [vp, C.c_int32]
         L.z4c_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.c_int32]
         _lib = L
@@ -303,6 +311,51 @@ class Pack:
         self._check(lib().z4c_rhs(self.h, src_reg, C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
 
+    def psi4(self, reg: int = REG_U, origin=(0.0, 0.0, 0.0), out=None, stream=None):
+        """z4c_psi4: device tensor, interior layout with 2 components (Re, Im)."""
+        import torch
+        if out is None:
+            out = torch.empty(2 * self.zones, dtype=torch.float64, device=self.regs[0].device)
+        o = (C.c_double * 3)(*origin)
+        self._check(lib().z4c_psi4(self.h, reg, o, C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def _points(self, points):
+        import torch
+        p = torch.as_tensor(np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3),
+                            device=self.regs[0].device)
+        return p, int(p.shape[0])
+
+    def interp(self, src, ncomp: int, points, stream=None):
+        """z4c_interp of an interior-layout device tensor at points -> (npts, ncomp)."""
+        import torch
+        p, npts = self._points(points)
+        out = torch.empty(npts * ncomp, dtype=torch.float64, device=p.device)
+        self._check(lib().z4c_interp(self.h, C.c_void_p(src.data_ptr()), ncomp, C.c_void_p(p.data_ptr()),
+                                     npts, C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out.cpu().numpy().reshape(npts, ncomp)
+
+    def interp_state(self, reg: int, first: int, nfield: int, points, stream=None):
+        """z4c_interp_state: fields first..first+nfield-1 of `reg` at points."""
+        import torch
+        p, npts = self._points(points)
+        out = torch.empty(npts * nfield, dtype=torch.float64, device=p.device)
+        self._check(lib().z4c_interp_state(self.h, reg, first, nfield, C.c_void_p(p.data_ptr()), npts,
+                                           C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out.cpu().numpy().reshape(npts, nfield)
+
+    def tracker_set(self, positions, stream=None):
+        pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
+        self._check(lib().z4c_tracker_set(self.h, pos.shape[0], pos.ctypes.data_as(C.POINTER(C.c_double)),
+                                          _stream_ptr(stream)))
+        self._ntrack = pos.shape[0]
+
+    def tracker_get(self, stream=None):
+        n = getattr(self, "_ntrack", 0)
+        pos = np.zeros((max(n, 1), 3))
+        self._check(lib().z4c_tracker_get(self.h, pos.ctypes.data_as(C.POINTER(C.c_double)), _stream_ptr(stream)))
+        return pos[:n]
+
     def set_variant(self, variant: int, persistent: bool = False, stream=None):
         self._check(lib().z4c_set_variant(self.h, variant, 1 if persistent else 0, _stream_ptr(stream)))
 
@@ -410,6 +463,31 @@ def regrid_plan(mesh, params: dict, flags, level_max: int):
         return _plan(h, mesh, flags, level_max)
     finally:
         lib().z4c_pack_destroy(h)
+
+
+def swsh_project(values, points, weights, centre, lmax: int, device: str = "cuda"):
+    """z4c_swsh_project of complex values on a quadrature sphere:
+    {(l, m): C_lm} for l = 2..lmax."""
+    import torch
+    v = np.asarray(values, dtype=complex)
+    vals = torch.as_tensor(np.stack([v.real, v.imag], 1).reshape(-1).copy(), device=device)
+    p = torch.as_tensor(np.ascontiguousarray(points, dtype=np.float64).reshape(-1), device=device)
+    w = torch.as_tensor(np.ascontiguousarray(weights, dtype=np.float64), device=device)
+    nm = (lmax + 1) ** 2 - 4
+    out = torch.empty(2 * nm, dtype=torch.float64, device=device)
+    c = (C.c_double * 3)(*centre)
+    rc = lib().z4c_swsh_project(C.c_void_p(vals.data_ptr()), C.c_void_p(p.data_ptr()),
+                                C.c_void_p(w.data_ptr()), int(w.shape[0]), c, lmax,
+                                C.c_void_p(out.data_ptr()), None)
+    if rc:
+        raise Z4cError(rc, "z4c_swsh_project")
+    o = out.cpu().numpy()
+    res, q = {}, 0
+    for l in range(2, lmax + 1):
+        for m in range(-l, l + 1):
+            res[(l, m)] = complex(o[2 * q], o[2 * q + 1])
+            q += 1
+    return res
 
 
 # ---------------------------------------------------------------- learned part

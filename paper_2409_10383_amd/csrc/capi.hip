@@ -591,6 +591,7 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
     pk->ws_regrid = o; o = align256(o + sizeof(RegridDesc) * nblocks);
     pk->ws_vnbr = o;   o = align256(o + sizeof(int64_t) * 27 * nblocks);
     pk->ws_vmask = o;  o = align256(o + sizeof(uint32_t) * nblocks);
+    pk->ws_track = o;  o = align256(o + sizeof(double) * 9 * Z4C_MAXTRACK);
     pk->ws_total = o;
     pk->part_host.resize(16 * pk->work.size());
     pk->first_work.assign(nblocks + 1, 0);
@@ -812,6 +813,10 @@ int z4c_rk4_stage(z4c_pack* pk, int32_t stage, double dt, void* stream)
     static const int dst_of[5] = {0, Z4C_REG_S1, Z4C_REG_S2, Z4C_REG_S1, Z4C_REG_U};
     int rc = fill_impl(pk, src_of[stage], stream, true);
     if (rc) return rc;
+    if (pk->ntrack > 0) {
+        hipError_t te = track_stage(pk, stage, src_of[stage], dt, as_stream(stream));
+        if (te != hipSuccess) return fail(pk, Z4C_EDEVICE, "tracker launch: %s", hipGetErrorString(te));
+    }
     StageArgs a = stage_args(pk);
     a.src = pk->reg[src_of[stage]];
     a.dst = pk->reg[dst_of[stage]];

@@ -89,7 +89,6 @@ struct DiagArgs {
     double* partial;          // [nwork][8]
     const BlockDev* blocks;
     const WorkItem* work;
-    const int64_t* vnbr;      // per block, 27 direction offsets of the staged halo
     ParamsDev P;
     double lo[3];
     int32_t ncentres;

@@ -36,6 +36,10 @@ struct z4c_pack {
     std::vector<int64_t> vnbr;    // virtual halos: 27 offsets per block
     std::vector<uint32_t> vmask;  // virtual-halo directions per block
     int virt_x = 1;               // 0: only directions with dx = 0 are virtual
+    // puncture tracker: device state (x, k_prev, acc) per puncture in the workspace
+    int ntrack = 0;
+    size_t ws_track = 0;
+    std::vector<double> track_host;
     size_t ws_first = 0, ws_feat = 0, ws_x = 0, ws_y = 0;
     std::vector<int32_t> first_work;
     int maxghost = 0;
@@ -74,5 +78,7 @@ hipStream_t as_stream(void* s);
 int64_t floor_div(int64_t a, int64_t b);
 // Lagrange weights of the nodes q + 1/2, q = 0..n-1, at t
 void lagrange_half(int n, double t, double* w);
+// RK4 stage `stage` of the puncture tracker (no-op without punctures)
+hipError_t track_stage(z4c_pack* pk, int stage, int reg, double dt, hipStream_t s);
 
 }  // namespace z4c_host
