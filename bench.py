@@ -143,6 +143,7 @@ def extra_runs(z4c, zi, torch):
         mesh, p, data, dt, _ = zi.workload("bl64x32")
         pk = z4c.Pack(mesh, p, z4c.FP32_MIXED)
         pk.upload(z4c.REG_U, data)
+        chosen32, _ = pk.autotune(reps=3, stream=s)
         pk.rk4_step(dt, 2, stream=s)
         s.synchronize()
         e0.record(s)
@@ -150,7 +151,9 @@ def extra_runs(z4c, zi, torch):
         e1.record(s)
         s.synchronize()
         ms = e0.elapsed_time(e1)
-        out["fp32_storage_bl64x32"] = {"zcps": pk.zones * 10 / (ms * 1e-3)}
+        out["fp32_storage_bl64x32"] = {"zcps": pk.zones * 10 / (ms * 1e-3),
+                                       "tile": "x".join(str(v) for v in z4c.TILE_SHAPES[chosen32 // 2]),
+                                       "persistent": bool(chosen32 % 2)}
         del pk
         torch.cuda.empty_cache()
     return out

@@ -224,11 +224,12 @@ int z4c_rk4_step(struct z4c_pack *pack, double dt, int32_t nsteps, void *stream)
  * not divide every block.  Synchronises the stream. */
 int z4c_set_variant(struct z4c_pack *pack, int32_t variant, int32_t persistent, void *stream);
 
-/* Autotuner: times `reps` RHS launches of every (variant, persistent)
- * pair that fits the pack, times_ms[2*variant + persistent] (host, 8
- * doubles, -1 where not applicable, nullable), selects the fastest and
- * returns its index in *chosen.  Uses the accumulator register as scratch
- * (call between RK4 steps).  Synchronises the stream. */
+/* Autotuner: times `reps` RK4 stage-1 launches with dt = 0 (ghost fill
+ * included) of every (variant, persistent) pair that fits the pack,
+ * times_ms[2*variant + persistent] (host, 8 doubles, -1 where not
+ * applicable, nullable), selects the fastest and returns its index in
+ * *chosen.  Overwrites S1 and the accumulator, leaves U unchanged (call
+ * between RK4 steps).  Synchronises the stream. */
 int z4c_autotune(struct z4c_pack *pack, int32_t reps, double *times_ms, int32_t *chosen,
                  void *stream);
 

@@ -413,6 +413,23 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
 #pragma unroll
     for (int q = 0; q < 3; ++q) Gam[q] = (C)srcb[(F_GAMX + q) * slab + cz];
 
+    // RK inputs of this zone (U for stages 1-3, the accumulator for 2-4).
+    // FP64: loaded before the algebra so that their latency overlaps it (the
+    // values wait in the AGPR half of the register file).  FP32 storage keeps
+    // them out of the registers (its kernels fit two waves per SIMD) and
+    // loads them in the update.
+    constexpr bool EARLY = sizeof(T) == 8;
+    const int64_t n3 = (int64_t)n * n * n;
+    const int64_t ci = B.ioff + ((int64_t)k * n + j) * n + i;
+    const T* __restrict__ U0 = (const T*)a.U + B.off + cz;
+    double upre[EARLY ? NF : 1], apre[EARLY ? NF : 1];
+    if constexpr (EARLY) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            upre[f] = (a.stage >= 1 && a.stage <= 3) ? (double)U0[f * slab] : 0.0;
+            apre[f] = (a.stage >= 2) ? a.A[ci + f * n3] : 0.0;
+        }
+    }
     C rhs[NF];
     z4c_algebra<C>(P, chi, gdn, gu, Kh, A, Gam, Th, al, be, dg, dchi, ddchi, dal, ddal, dbe, Lb,
                    Bj, eK, Rt, rhs);
@@ -420,8 +437,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     for (int f = 0; f < NF; ++f) rhs[f] += adks[f * 256 + t];
 
     // ---- RK4 stage update
-    const int64_t n3 = (int64_t)n * n * n;
-    const int64_t ci = B.ioff + ((int64_t)k * n + j) * n + i;
     if (a.stage == 0) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) a.rhs_out[ci + f * n3] = (double)rhs[f];
@@ -429,29 +444,47 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     }
     const double dt = a.dt;
     double out[NF];
-    const T* __restrict__ U = (const T*)a.U + B.off + cz;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         const double kf = (double)rhs[f];
         double* Af = a.A + ci + f * n3;
-        switch (a.stage) {
-        case 1: {
-            const double u = (double)U[f * slab];
-            out[f] = u + 0.5 * dt * kf;
-            *Af = u + dt / 6.0 * kf;
-        } break;
-        case 2: {
-            const double u = (double)U[f * slab];
-            out[f] = u + 0.5 * dt * kf;
-            *Af += dt / 3.0 * kf;
-        } break;
-        case 3: {
-            const double u = (double)U[f * slab];
-            out[f] = u + dt * kf;
-            *Af += dt / 3.0 * kf;
-        } break;
-        default:
-            out[f] = *Af + dt / 6.0 * kf;
+        if constexpr (EARLY) {
+            switch (a.stage) {
+            case 1:
+                out[f] = upre[f] + 0.5 * dt * kf;
+                *Af = upre[f] + dt / 6.0 * kf;
+                break;
+            case 2:
+                out[f] = upre[f] + 0.5 * dt * kf;
+                *Af = apre[f] + dt / 3.0 * kf;
+                break;
+            case 3:
+                out[f] = upre[f] + dt * kf;
+                *Af = apre[f] + dt / 3.0 * kf;
+                break;
+            default:
+                out[f] = apre[f] + dt / 6.0 * kf;
+            }
+        } else {
+            switch (a.stage) {
+            case 1: {
+                const double u = (double)U0[f * slab];
+                out[f] = u + 0.5 * dt * kf;
+                *Af = u + dt / 6.0 * kf;
+            } break;
+            case 2: {
+                const double u = (double)U0[f * slab];
+                out[f] = u + 0.5 * dt * kf;
+                *Af += dt / 3.0 * kf;
+            } break;
+            case 3: {
+                const double u = (double)U0[f * slab];
+                out[f] = u + dt * kf;
+                *Af += dt / 3.0 * kf;
+            } break;
+            default:
+                out[f] = *Af + dt / 6.0 * kf;
+            }
         }
     }
     if (P.enforce) enforce_zone(out, P);
