@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--workload", default="bl64x32")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", default=None,
+                    help="fixed stage-kernel launch instead of the autotuner's choice: variant "
+                         "index 0-3 (8x8x4, 16x4x4, 8x4x8, 16x8x2), suffix p = persistent")
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP32 and batched multi-level measurements")
@@ -71,7 +74,8 @@ def cpu_baseline(workload):
 
 
 def _pmc_rows(d, counter):
-    """(kernel name, counter value in KiB) per dispatch from a rocprofv3 csv run."""
+    """(kernel name, counter value in KiB) per dispatch, in dispatch order,
+    from a rocprofv3 csv run."""
     import csv
     import glob
     rows = []
@@ -79,26 +83,30 @@ def _pmc_rows(d, counter):
         with open(f) as fh:
             for r in csv.DictReader(fh):
                 if r.get("Counter_Name") == counter:
-                    rows.append((r.get("Kernel_Name", ""), float(r["Counter_Value"])))
-    return rows
+                    rows.append((int(r["Dispatch_Id"]), r.get("Kernel_Name", ""), float(r["Counter_Value"])))
+    return [(k, v) for _, k, v in sorted(rows)]
 
 
 def summarize_pmc(args):
     """HBM bytes per stage-kernel launch from FETCH_SIZE and WRITE_SIZE,
-    each scaled by what the same counter reads for a 1 GiB device copy."""
+    each scaled by what the same counter reads for a 1 GiB device copy.
+    Only the last 8 stage-kernel dispatches count: the four RK stages of
+    the timed step and of the profiled step of a `--steps 1
+    --profile-steps 1` run (the autotuner's trial launches come before)."""
     out = {"workload": args.workload, "precision": args.precision, "kernel_source_hash": kernel_hash()}
     total = 0.0
     for d, ctr in zip(args.summarize_pmc, ("FETCH_SIZE", "WRITE_SIZE")):
         rows = _pmc_rows(d, ctr)
-        stage = [v for k, v in rows if "k_stage" in k]
+        stage = [v for k, v in rows if "k_stage" in k][-8:]
         copy = [v for k, v in rows if ("copy" in k.lower() or "elementwise" in k.lower())
                 and v > 0.5 * 1024 * 1024]
         if not stage or not copy:
             raise SystemExit(f"no k_stage or copy dispatches with {ctr} in {d}")
         factor = (1 << 30) / (max(copy) * 1024.0)
         kib = sum(stage) / len(stage)
-        out[ctr] = {"stage_kib_per_dispatch": kib, "copy_kib": max(copy), "scale": factor,
-                    "bytes_per_launch": kib * 1024.0 * factor}
+        out[ctr] = {"stage_kib_per_dispatch": kib, "dispatches": len(stage), "copy_kib": max(copy),
+                    "scale": factor, "bytes_per_launch": kib * 1024.0 * factor,
+                    "kernel": [k for k, v in rows if "k_stage" in k][-1]}
         total += kib * 1024.0 * factor
     out["bytes_per_launch"] = total
     path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.precision}.json")
@@ -179,7 +187,11 @@ def main():
     pack.upload(z4c.REG_U, data)
     stream = torch.cuda.current_stream()
     # tile shape and launch mode from the built-in autotuner (state unchanged)
-    chosen, _ = pack.autotune(reps=3)
+    if args.tile is None:
+        chosen, _ = pack.autotune(reps=3)
+    else:
+        chosen = 2 * int(args.tile[0]) + (1 if args.tile.endswith("p") else 0)
+        pack.set_variant(chosen // 2, bool(chosen % 2))
     for _ in range(args.warmup):
         pack.rk4_step(dt, 1)
     torch.cuda.synchronize()
