@@ -9,7 +9,9 @@
 //     and second derivatives, the odd (advective) and even (advective +
 //     Kreiss-Oliger) parts of the upwind-biased operator;
 //   - mixed second derivatives in two passes, d_x f then d_y(d_x f),
-//     d_z(d_x f), d_z(d_y f), through LDS intermediates;
+//     d_z(d_x f), d_z(d_y f), through LDS intermediates (the first pass
+//     covers only the halo points; the tile's own d_x f, d_y f are the
+//     axis sweep's);
 //   - second derivatives are contracted into the Ricci tensor and the shift
 //     terms as soon as they are produced, so only first derivatives and a
 //     few accumulators stay live in registers.
@@ -29,8 +31,14 @@ template <int N, int TX, int TY, int TZ> struct TileGeom {
     static constexpr int SX = TX + 2 * R, SY = TY + 2 * R, SZ = TZ + 2 * R;
     static constexpr int NS = SX * SY * SZ;         // staged cells
     static constexpr int DXY = TY + 2 * N, DXZ = TZ + 2 * N;
-    static constexpr int NDX = TX * DXY * DXZ;      // d_x f on y, z halos
-    static constexpr int NDY = TX * TY * DXZ;       // d_y f on a z halo
+    static constexpr int NDX = TX * DXY * DXZ;      // d_x f box over the y, z halos
+    static constexpr int NDY = TX * TY * DXZ;       // d_y f box over the z halo
+    // points of those boxes the mixed derivatives read outside the tile:
+    // d_x f on the y halo (TX x 2N x TZ) and the z halo (TX x TY x 2N), d_y f
+    // on the z halo; the tile's own values come from the axis sweeps
+    static constexpr int NHXY = TX * 2 * N * TZ;
+    static constexpr int NHX = NHXY + TX * TY * 2 * N;
+    static constexpr int NHY = TX * TY * 2 * N;
 };
 
 // LDS per workgroup: NBUF staged-field buffers, the mixed-derivative
@@ -171,37 +179,48 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
 
     // origin of the staged tile (tile + halo R) in the ghosted block
     const int64_t base0 = ((int64_t)(w.k0 - R + g) * E + (w.j0 - R + g)) * E + (w.i0 - R + g);
-    // d_x f on the y/z halo and d_y f on the z halo (for mixed derivatives);
-    // the staged-tile index of each of this thread's points is fixed per tile
-    constexpr int NQX = (G::NDX + 255) / 256, NQY = (G::NDY + 255) / 256;
+    // d_x f on the y/z halos and d_y f on the z halo (for mixed derivatives):
+    // each of this thread's halo points keeps its staged-tile index (high 16
+    // bits) and its index in the d_x f / d_y f box (low 16 bits), fixed per tile
+    static_assert(G::NS < 65536 && G::NDX < 65536, "halo point indices must fit 16 bits");
+    constexpr int NQX = (G::NHX + 255) / 256, NQY = (G::NHY + 255) / 256;
+    constexpr int N2 = 2 * N;
     int ccx[NQX], ccy[NQY];
+    auto halo = [](int zz, int ext) { return zz < N ? zz - N : ext + zz - N; };
 #pragma unroll
     for (int r = 0; r < NQX; ++r) {
         const int q = t + 256 * r;
-        const int x = q % TX, y = (q / TX) % G::DXY, z = q / (TX * G::DXY);
-        ccx[r] = ((z + R - N) * SY + (y + R - N)) * SX + (x + R);
+        int x, y, z;
+        if (q < G::NHXY) {
+            x = q % TX; y = halo((q / TX) % N2, TY); z = q / (TX * N2);
+        } else {
+            const int u = q - G::NHXY;
+            x = u % TX; y = (u / TX) % TY; z = halo(u / (TX * TY), TZ);
+        }
+        ccx[r] = ((((z + R) * SY + (y + R)) * SX + (x + R)) << 16) | (((z + N) * G::DXY + (y + N)) * TX + x);
     }
 #pragma unroll
     for (int r = 0; r < NQY; ++r) {
         const int q = t + 256 * r;
-        const int x = q % TX, y = (q / TX) % TY, z = q / (TX * TY);
-        ccy[r] = ((z + R - N) * SY + (y + R)) * SX + (x + R);
+        const int x = q % TX, y = (q / TX) % TY, z = halo(q / (TX * TY), TZ);
+        ccy[r] = ((((z + R) * SY + (y + R)) * SX + (x + R)) << 16) | (((z + N) * TY + y) * TX + x);
     }
     auto first_pass = [&]() {
 #pragma unroll
         for (int r = 0; r < NQX; ++r)
-            if (t + 256 * r < G::NDX) dxs[t + 256 * r] = fd1<N, C>(cur + ccx[r], 1);
+            if (t + 256 * r < G::NHX) dxs[ccx[r] & 0xFFFF] = fd1<N, C>(cur + (ccx[r] >> 16), 1);
 #pragma unroll
         for (int r = 0; r < NQY; ++r)
-            if (t + 256 * r < G::NDY) dys[t + 256 * r] = fd1<N, C>(cur + ccy[r], SX);
+            if (t + 256 * r < G::NHY) dys[ccy[r] & 0xFFFF] = fd1<N, C>(cur + (ccy[r] >> 16), SX);
     };
+    // this zone's own entries of the two boxes (written by the axis sweep)
+    const int own_x = ((tz + N) * G::DXY + (ty + N)) * TX + tx;
+    const int own_y = ((tz + N) * TY + ty) * TX + tx;
     // mixed derivatives of the staged field at this zone: xy, xz, yz
     auto mixed = [&](C& mxy, C& mxz, C& myz) {
-        const int cx = ((tz + N) * G::DXY + (ty + N)) * TX + tx;
-        const int cy = ((tz + N) * TY + ty) * TX + tx;
-        mxy = fd1<N, C>(dxs + cx, TX);
-        mxz = fd1<N, C>(dxs + cx, TX * G::DXY);
-        myz = fd1<N, C>(dys + cy, TX * TY);
+        mxy = fd1<N, C>(dxs + own_x, TX);
+        mxz = fd1<N, C>(dxs + own_x, TX * G::DXY);
+        myz = fd1<N, C>(dys + own_y, TX * TY);
     };
 
     // ---- centre values needed before the sweep: shift, conformal metric
@@ -231,7 +250,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     for (int q = 0; q < 3; ++q) { Lb[q] = 0; Bj[q] = 0; eK[q] = 0; }
 
     // generic per-field sweep: first derivatives d1[3], pure second d2[3]
-    // advection + dissipation of field f at this zone, kept in LDS
+    // advection + dissipation of field f at this zone, kept in LDS.  Fields
+    // with second derivatives also need mixed ones: the sweep then leaves the
+    // zone's d_x f and d_y f (no 1/h) in the boxes the mixed pass reads.
     auto put_adk = [&](int f, C v) { adks[f * 256 + t] = v; };
     auto sweep = [&](int f, bool gauge_field, C* d1, C* d2, auto D1tag, auto D2tag) {
         constexpr bool WD1 = decltype(D1tag)::value, WD2 = decltype(D2tag)::value;
@@ -241,6 +262,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
         for (int d = 0; d < 3; ++d) {
             C x1, x2;
             axis_pass<N, C, WD1, WD2>(cur, c, st3[d], a_on ? be[d] : (C)0, sig, x1, x2, ad);
+            if (WD2 && d == 0) dxs[own_x] = x1;
+            if (WD2 && d == 1) dys[own_y] = x1;
             if (WD1) d1[d] = x1 * ih;
             if (WD2) d2[d] = x2 * ih2;
         }
@@ -311,9 +334,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
             // conformal metric: first derivatives, Ricci second-derivative term
             const int p = sl;
             first_pass();
-            lds_barrier();
             C d1[3], d2[3], mxy, mxz, myz;
             sweep(F_GXX + p, false, d1, d2, T1(), T1());
+            lds_barrier();
             mixed(mxy, mxz, myz);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -329,10 +352,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
         } else if (sl < 8) {
             // chi and alpha: first and second derivatives
             first_pass();
-            lds_barrier();
             C d1[3], d2[3], mxy, mxz, myz;
             const bool is_chi = sl == 6;
             sweep(is_chi ? F_CHI : F_ALPHA, !is_chi, d1, d2, T1(), T1());
+            lds_barrier();
             mixed(mxy, mxz, myz);
             C* dd = is_chi ? ddchi : ddal;
             C* d = is_chi ? dchi : dal;
@@ -343,9 +366,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
             // shift: first derivatives, g~^jk d_j d_k beta^i and d_j d_k beta^k
             const int q = sl - 8;
             first_pass();
-            lds_barrier();
             C d1[3], d2[3], mxy, mxz, myz;
             sweep(F_BETAX + q, true, d1, d2, T1(), T1());
+            lds_barrier();
             mixed(mxy, mxz, myz);
             mxy *= ih2; mxz *= ih2; myz *= ih2;
             const C dd[6] = {d2[0], mxy, mxz, d2[1], myz, d2[2]};
