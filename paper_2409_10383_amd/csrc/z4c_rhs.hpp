@@ -119,6 +119,19 @@ __device__ __forceinline__ void ricci(const C (&gdn)[6], const C (&gu)[6], const
                                       const C (&dchi)[3], const C (&ddchi)[6], C (&Rt)[6],
                                       C (&Rij)[6], C& Rs)
 {
+    // the quadratic Christoffel terms
+    //   g~^lm (G~^k_li G~_jkm + G~^k_lj G~_ikm + G~^k_im G~_klj)
+    // contract as sum_kl (G~^k_li H_jk^l + G~^k_lj H_ik^l + G~^k_il H_kj^l)
+    // with H_jk^l = g~^lm G~_jkm (27 values instead of a 3 x 3 x 3 sum per
+    // (l, m) pair)
+    C H[3][3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+                H[j][k][l] = gu[S(l, 0)] * Gl[j][S(k, 0)] + gu[S(l, 1)] * Gl[j][S(k, 1)] + gu[S(l, 2)] * Gl[j][S(k, 2)];
 #pragma unroll
     for (int p = 0; p < 6; ++p) {
         const int i = SA(p), j = SB(p);
@@ -126,16 +139,10 @@ __device__ __forceinline__ void ricci(const C (&gdn)[6], const C (&gu)[6], const
 #pragma unroll
         for (int k = 0; k < 3; ++k) s += Gd[k] * (C)0.5 * (Gl[i][S(j, k)] + Gl[j][S(i, k)]);
 #pragma unroll
-        for (int l = 0; l < 3; ++l)
+        for (int k = 0; k < 3; ++k)
 #pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                C t = 0;
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-                    t += Gu[k][S(l, i)] * Gl[j][S(k, m)] + Gu[k][S(l, j)] * Gl[i][S(k, m)] +
-                         Gu[k][S(i, m)] * Gl[k][S(l, j)];
-                s += gu[S(l, m)] * t;
-            }
+            for (int l = 0; l < 3; ++l)
+                s += Gu[k][S(l, i)] * H[j][k][l] + Gu[k][S(l, j)] * H[i][k][l] + Gu[k][S(i, l)] * H[k][j][l];
         Rt[p] += s;
     }
     C Dchi[6], trD = 0, dc2 = 0;
