@@ -87,13 +87,32 @@ def _pmc_rows(d, counter):
     return [(k, v) for _, k, v in sorted(rows)]
 
 
+def variant_key(chosen):
+    """Launch label of a stage-kernel variant: tile shape, p = persistent."""
+    from paper_2409_10383_amd import TILE_SHAPES
+    return "x".join(str(v) for v in TILE_SHAPES[chosen // 2]) + ("p" if chosen % 2 else "")
+
+
 def summarize_pmc(args):
     """HBM bytes per stage-kernel launch from FETCH_SIZE and WRITE_SIZE,
-    each scaled by what the same counter reads for a 1 GiB device copy.
-    Only the last 8 stage-kernel dispatches count: the four RK stages of
-    the timed step and of the profiled step of a `--steps 1
-    --profile-steps 1` run (the autotuner's trial launches come before)."""
-    out = {"workload": args.workload, "precision": args.precision, "kernel_source_hash": kernel_hash()}
+    each scaled by what the same counter reads for a 1 GiB device copy, for
+    the launch variant the counter runs used (--tile, required).  Only the
+    last 8 stage-kernel dispatches count: the four RK stages of the timed
+    step and of the profiled step of a `--steps 1 --profile-steps 1` run.
+    The figures of each variant are kept side by side in the file, which is
+    started afresh when the kernel sources change."""
+    if args.tile is None:
+        raise SystemExit("--summarize-pmc needs the --tile the counter runs used")
+    key = variant_key(2 * int(args.tile[0]) + (1 if args.tile.endswith("p") else 0))
+    path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.precision}.json")
+    doc = {"workload": args.workload, "precision": args.precision, "kernel_source_hash": kernel_hash(),
+           "variants": {}}
+    if os.path.exists(path):
+        with open(path) as f:
+            old = json.load(f)
+        if old.get("kernel_source_hash") == doc["kernel_source_hash"] and "variants" in old:
+            doc["variants"] = old["variants"]
+    out = {}
     total = 0.0
     for d, ctr in zip(args.summarize_pmc, ("FETCH_SIZE", "WRITE_SIZE")):
         rows = _pmc_rows(d, ctr)
@@ -109,10 +128,11 @@ def summarize_pmc(args):
                     "kernel": [k for k, v in rows if "k_stage" in k][-1]}
         total += kib * 1024.0 * factor
     out["bytes_per_launch"] = total
-    path = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.precision}.json")
+    doc["variants"][key] = out
+    doc["variants"] = dict(sorted(doc["variants"].items()))
     with open(path, "w") as f:
-        json.dump(out, f, indent=1)
-    print(json.dumps(out))
+        json.dump(doc, f, indent=1)
+    print(json.dumps({key: out}))
 
 
 def copy_calibration():
@@ -222,7 +242,7 @@ def main():
         with open(tfile) as f:
             t = json.load(f)
         if t.get("kernel_source_hash") == kernel_hash():
-            traffic = t.get("bytes_per_launch")
+            traffic = t.get("variants", {}).get(variant_key(chosen), {}).get("bytes_per_launch")
 
     out = {
         "metric": METRIC,
@@ -261,12 +281,16 @@ def main():
 
 
 def kernel_hash():
+    """Hash of the sources that decide the stage kernel's memory traffic:
+    its own file, the host code that builds its work list and launches it,
+    and every shared header."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2409_10383_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(fh.read())
+        if f in ("stage.hip", "capi.hip") or f.endswith(".hpp"):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -93,4 +93,7 @@ def test_invalid_descriptions_rejected():
     assert _create(finer, p) == -1
     assert _create(fine, p) == 0
     assert _create(mesh, p, precision=3) == -1
+    h = C.c_void_p()                                          # empty pack
+    assert z.lib().z4c_pack_create(C.byref(z.make_params(mesh, p)), z.make_blocks(mesh), 0,
+                                   C.byref(h)) == -1
     assert _create(mesh, dict(p, terms=99)) == -1

@@ -163,6 +163,23 @@ def test_bl64x32_full_size_rhs_parity():
     assert_parity(rg, ora_rhs(mesh, p, data), what="rhs bl64x32")
 
 
+def test_bl64x32_full_size_step_in_bench_launch_configuration():
+    """One RK4 step of the full 64 x 32^3 pack exactly as the benchmark runs
+    it (tile shape and launch mode from the autotuner, same dt) against one
+    oracle step of the whole mesh: every zone of every field."""
+    mesh, p, data, dt, _ = zi.workload("bl64x32")
+    pk = z().Pack(mesh, p)
+    pk.upload(z().REG_U, data)
+    chosen, _ = pk.autotune(reps=1)
+    pk.rk4_step(dt, 1)
+    torch.cuda.synchronize()
+    got = pk.download(z().REG_U)
+    om = oracle.OracleMesh(mesh)
+    regs = oracle.Registers(om, data)
+    oracle.rk4_steps(regs, p, dt, 1)
+    assert_parity(got, om.interiors(regs.U), what=f"step bl64x32 (variant {chosen})", mode="state")
+
+
 # tile counts that are not a multiple of 8 (the XCD-interleaved slot map has
 # a short last slice): one 24^3 block = 54 tiles, 3x3x1 blocks of 8^3 = 18
 RAGGED = {"one24": ((1, 1, 1), 24, (6.0, 6.0, 6.0)), "three_by_three8": ((3, 3, 1), 8, (6.0, 6.0, 2.0))}
