@@ -176,6 +176,13 @@ int build_xlevel(z4c_pack* pk)
     const int64_t per256 = 256 / (int64_t)esz;
     const int nb = (int)pk->blk.size();
     pk->img_off.assign(nb, -1);
+    // image rows (z-plane * m + y) some transfer reads, per source block
+    std::vector<std::vector<uint8_t>> img_rows(nb);
+    auto need_row = [&](int F, int64_t ic) {
+        const int64_t m = pk->blk[F].n / 2;
+        if (img_rows[F].empty()) img_rows[F].assign((size_t)(m * m), 0);
+        img_rows[F][(size_t)(ic / m)] = 1;
+    };
     pk->img_fstride.assign(nb, 0);
     // coarse image of fine block F (allocated on first use)
     auto image_of = [&](int F) -> int64_t {
@@ -217,6 +224,7 @@ int build_xlevel(z4c_pack* pk)
                         it.dst_stride = (int32_t)D.slab;
                         const int64_t ic = geo.image_cell(F, Gb);
                         if (ic < 0) return Z4C_EINVAL;
+                        need_row(F, ic);
                         it.src = image_of(F) + ic;
                         it.src_stride = pk->img_fstride[F];
                         it.kind = 1;
@@ -278,6 +286,7 @@ int build_xlevel(z4c_pack* pk)
                                     if (Fb < 0) return Z4C_EINVAL;  // would need a level two away
                                     const int64_t ic = geo.image_cell(Fb, Kb);
                                     if (ic < 0) return Z4C_EINVAL;
+                                    need_row(Fb, ic);
                                     it.src = image_of(Fb) + ic;
                                     it.src_stride = pk->img_fstride[Fb];
                                     it.kind = 3;
@@ -317,7 +326,8 @@ int build_xlevel(z4c_pack* pk)
                 }
     }
     // image restriction work: per source block, coarse z-slices split into
-    // row chunks that fit the LDS budget
+    // row chunks that fit the LDS budget; only chunks holding rows that a
+    // transfer reads are computed, each trimmed to its first and last such row
     for (int F = 0; F < nb; ++F) {
         if (pk->img_off[F] < 0) continue;
         const int m = pk->blk[F].n / 2;
@@ -326,15 +336,23 @@ int build_xlevel(z4c_pack* pk)
         int cy = m;
         while (cy > 1 && ((int64_t)m * (2 * cy + np) * np > RI_XMAX || (int64_t)m * cy * np > RI_YMAX)) cy /= 2;
         if ((int64_t)m * (2 * cy + np) * np > RI_XMAX || (int64_t)m * cy * np > RI_YMAX) return Z4C_EUNSUPPORTED;
+        const std::vector<uint8_t>& need = img_rows[F];
         for (int kz = 0; kz < m; ++kz)
             for (int y0 = 0; y0 < m; y0 += cy) {
+                int lo = -1, hi = -1;
+                for (int y = y0; y < std::min(y0 + cy, m); ++y)
+                    if (need[(size_t)kz * m + y]) {
+                        if (lo < 0) lo = y;
+                        hi = y;
+                    }
+                if (lo < 0) continue;
                 ImageSlice sl;
                 sl.img = pk->img_off[F];
                 sl.block = F;
                 sl.fstride = pk->img_fstride[F];
                 sl.kz = (int16_t)kz;
-                sl.y0 = (int16_t)y0;
-                sl.ny = (int16_t)std::min(cy, m - y0);
+                sl.y0 = (int16_t)lo;
+                sl.ny = (int16_t)(hi - lo + 1);
                 sl.pad = 0;
                 pk->islice.push_back(sl);
             }

@@ -187,7 +187,8 @@ __global__ __launch_bounds__(256) void k_prolong(const XlevelArgs a)
 }
 
 // grouped prolongation: one coarse parent, up to 8 fine children, separable
-// (x, then y, then z) over the union stencil
+// (x, then y, then z) over the union stencil; one thread per group and field
+// (grid y = field)
 template <class T, int NP>
 __global__ __launch_bounds__(256) void k_prolong_group(const XlevelArgs a)
 {
@@ -203,7 +204,8 @@ __global__ __launch_bounds__(256) void k_prolong_group(const XlevelArgs a)
     const int64_t se = it.se, E = B.E;
     const double* w0 = a.pw;           // parity 0 weights, union points 0..np-1
     const double* w1 = a.pw + 8;       // parity 1 weights, union points even..even+np-1
-    for (int f = 0; f < NF; ++f) {
+    {
+        const int f = blockIdx.y;
         const T* p = sh + (int64_t)f * it.fstride;
         double acc[2][2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
 #pragma unroll 1
@@ -244,7 +246,7 @@ static void launch_xlevel_np(const XlevelArgs& a, hipStream_t s)
     if (a.nislice) hipLaunchKernelGGL((k_restrict_image<T, NP>), dim3((unsigned)a.nislice), dim3(256), 0, s, a);
     if (gx) hipLaunchKernelGGL(k_xfer<T>, dim3(gx), dim3(256), 0, s, a);
     if (gp) hipLaunchKernelGGL(k_prolong<T>, dim3(gp), dim3(256), 0, s, a);
-    if (gg) hipLaunchKernelGGL((k_prolong_group<T, NP>), dim3(gg), dim3(256), 0, s, a);
+    if (gg) hipLaunchKernelGGL((k_prolong_group<T, NP>), dim3(gg, NF), dim3(256), 0, s, a);
 }
 
 template <class T>
