@@ -7,6 +7,15 @@
   python -m paper_2409_10383_amd.experiments learned
       4096 x 16^3 two-puncture pack: train the indicator on h-vs-2h labels of
       varied puncture setups and report flag agreement against dchi-max.
+  python -m paper_2409_10383_amd.experiments adaptive [--budget 64 --steps 16]
+      the same training, then the closed loop: the `budget` blocks of the
+      4096 x 16^3 pack of an unseen equal-mass setup that the learned
+      indicator ranks highest, or that dchi-max ranks highest, are flagged;
+      z4c_regrid_plan turns the flags into a refined mesh on which the
+      puncture data are set (prolongating chi through a puncture overshoots
+      below zero, so initial refinement re-evaluates the data, as mesh
+      generation does); each mesh and the unrefined one are evolved and
+      their constraint norms reported.
 
 Each prints one JSON object.  All arithmetic runs in libz4c.
 """
@@ -58,7 +67,10 @@ def precision(steps: int):
     print(json.dumps(out))
 
 
-def learned(nvariants: int = 6, epochs: int = 40):
+def _train(nvariants: int, epochs: int):
+    """The indicator trained on h-vs-2h labels of `nvariants` random
+    two-puncture setups on the 4096 x 16^3 pack; returns (net, snapshot,
+    test setups, training samples, final MSE)."""
     import torch
     import paper_2409_10383_amd as z4c
     import z4c_inputs as zi
@@ -107,6 +119,11 @@ def learned(nvariants: int = 6, epochs: int = 40):
     print(f"training on {T.numel()} blocks", file=sys.stderr, flush=True)
     loss = net.train(X, T, epochs=epochs, lr=3e-3, batch=4096)
     print(f"final training MSE {loss:.4f}", file=sys.stderr, flush=True)
+    return net, snapshot, test, int(T.numel()), loss
+
+
+def learned(nvariants: int = 6, epochs: int = 40):
+    net, snapshot, test, ntrain, loss = _train(nvariants, epochs)
     rows = []
     for v in test:
         F, Y, D = snapshot(*v, steps=(0,))
@@ -117,19 +134,75 @@ def learned(nvariants: int = 6, epochs: int = 40):
             rows.append({"setup": list(map(float, v)), "K": K,
                          "learned_precision": len(truth & set(np.argsort(-pred)[:K])) / K,
                          "dchi_max_precision": len(truth & set(np.argsort(-f[:, 0])[:K])) / K})
-    print(json.dumps({"workload": "bbh4096x16", "train_samples": int(T.numel()),
+    print(json.dumps({"workload": "bbh4096x16", "train_samples": ntrain,
                       "final_mse": loss, "test": rows}))
+
+
+def adaptive(budget: int = 64, steps: int = 16, nvariants: int = 6, epochs: int = 40):
+    import torch
+    import paper_2409_10383_amd as z4c
+    import z4c_inputs as zi
+    net, _, test, ntrain, loss = _train(nvariants, epochs)
+    p = zi.params_default(6)
+    mesh = zi.uniform_mesh((16, 16, 16), 16, 4, (-16.0,) * 3, (16.0,) * 3, zi.BC_OUTFLOW)
+    m1, m2, xp, yp = test[0]
+    punct = [(xp, yp, 0.0), (-xp, -yp, 0.0)]
+    data = zi.brill_lindquist(mesh, [(m1, punct[0]), (m2, punct[1])])
+    base = z4c.Pack(mesh, p)
+    base.upload(z4c.REG_U, data)
+    base.fill_ghosts()
+    masses = [(m1, punct[0]), (m2, punct[1])]
+    dev = torch.empty(mesh.nb * 16, dtype=torch.float64, device="cuda")
+    feat = z4c.features(base, device_out=dev)
+    pred = net.forward(net.normalize(dev.view(mesh.nb, 16))).cpu().numpy()
+    ranks = {"learned": np.argsort(-pred)[:budget], "dchi_max": np.argsort(-feat[:, 0])[:budget]}
+    runs = {}
+    for name in ("none", "learned", "dchi_max"):
+        if name == "none":
+            pk = z4c.Pack(mesh, p)
+            pk.upload(z4c.REG_U, data)
+        else:
+            flags = np.zeros(mesh.nb, np.int8)
+            flags[ranks[name]] = 1
+            new = base.regrid_plan(flags, level_max=1)
+            pk = z4c.Pack(new, p)
+            pk.upload(z4c.REG_U, zi.brill_lindquist(new, masses))
+        # every mesh evolves to t = steps * 0.25 dx of the unrefined mesh
+        dt = 0.25 * pk.mesh.dx_min()
+        nst = int(round(steps * 0.25 * mesh.dx_min() / dt))
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        pk.rk4_step(dt, nst)
+        t1.record()
+        torch.cuda.synchronize()
+        _, nf = pk.constraints(per_zone=False)
+        _, ne = pk.constraints(per_zone=False, exclude=punct, r_exc=1.0)
+        runs[name] = {"blocks": int(pk.mesh.nb), "zones": int(pk.zones), "dt": dt, "steps": nst,
+                      "t_end": dt * nst, "ms": t0.elapsed_time(t1),
+                      "H_L2": float(nf[0]), "H_Linf": float(nf[1]), "M_L2": float(nf[2]),
+                      "H_L2_excised_r1": float(ne[0])}
+        print(f"{name}: {runs[name]}", file=sys.stderr, flush=True)
+        del pk
+        torch.cuda.empty_cache()
+    overlap = len(set(ranks["learned"].tolist()) & set(ranks["dchi_max"].tolist()))
+    print(json.dumps({"workload": "bbh4096x16 adaptive", "setup": list(map(float, test[0])),
+                      "budget_blocks": budget, "train_samples": ntrain, "final_mse": loss,
+                      "flag_overlap": overlap, "runs": runs}))
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["precision", "learned"])
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("what", choices=["precision", "learned", "adaptive"])
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--budget", type=int, default=64)
     a = ap.parse_args(argv)
     if a.what == "precision":
-        precision(a.steps)
-    else:
+        precision(a.steps or 100)
+    elif a.what == "learned":
         learned()
+    else:
+        adaptive(a.budget, a.steps or 16)
 
 
 if __name__ == "__main__":

@@ -47,7 +47,7 @@ def test_variants_bitwise_identical(order):
 
 def test_graph_replay_matches_eager():
     mesh, p, data = mixed_pack(8)
-    dt = 0.25 * mesh.dx(int(mesh.level.max()))
+    dt = 0.25 * mesh.dx_min()
     eager = z().Pack(mesh, p)
     eager.upload(z().REG_U, data)
     pg = dict(p, graph=1)

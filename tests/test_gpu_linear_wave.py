@@ -60,7 +60,7 @@ def evolve(mesh, cfl=0.25, order=6):
     fn = an.linear_wave_diagonal(1e-8, 1.0)
     data = [an.adm_to_z4c(fn, 0.0, *mesh.grid(b)) for b in range(mesh.nb)]
     p = zi.params_default(order)
-    hmin = mesh.dx(int(mesh.level.max()))
+    hmin = mesh.dx_min()
     nst = int(math.ceil(fn.period / (cfl * hmin)))
     pk = z().Pack(mesh, p)
     pk.upload(z().REG_U, data)

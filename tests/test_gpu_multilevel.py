@@ -65,7 +65,7 @@ def test_cross_level_rhs_and_step(order):
     om = oracle.OracleMesh(mesh)
     ro = oracle.rhs(om, p, om.scatter(data))
     assert_parity(rg, ro, what="rhs")
-    dt = 0.25 * mesh.dx(int(np.argmax(mesh.level)))
+    dt = 0.25 * mesh.dx_min()
     pk.rk4_step(dt, 1)
     regs = oracle.Registers(om, data)
     oracle.rk4_steps(regs, p, dt, 1)
@@ -105,6 +105,6 @@ def test_bbh512mixed_full_size():
     sample = sorted(set(int(b) for b in sample))
     ro = oracle.rhs(om, p, u, fill=False, blocks=sample)
     S = max(np.abs(data[b][[0, 1, 4, 6, 18]]).max() for b in sample)
-    hmin = mesh.dx(int(mesh.level.max()))
+    hmin = mesh.dx_min()
     assert_parity([rg[b] for b in sample], [ro[b] for b in sample], what="rhs bbh512mixed sample",
                   mode="rounding", S=S, order=8, h=hmin)

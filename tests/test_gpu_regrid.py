@@ -95,7 +95,7 @@ def test_adaptive_cycle_matches_oracle():
     assert np.array_equal(flags, oflags)
     assert flags.max() == 1
     new = pk.regrid(flags, 3)
-    dt = 0.25 * new.mesh.dx(int(new.mesh.level.max()))
+    dt = 0.25 * new.mesh.dx_min()
     new.rk4_step(dt, 1)
     torch.cuda.synchronize()
     omesh = rg.plan(mesh, oflags, 3)

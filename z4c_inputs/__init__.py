@@ -46,7 +46,12 @@ class Mesh:
         return int(self.level.shape[0])
 
     def dx(self, b: int) -> float:
+        """Cell size of block b."""
         return self.dx0 / (1 << int(self.level[b]))
+
+    def dx_min(self) -> float:
+        """Cell size of the finest level present."""
+        return self.dx0 / (1 << int(self.level.max()))
 
     def centres(self, b: int):
         """1D cell-centre coordinates of block b along x, y, z."""
@@ -310,7 +315,7 @@ def workload(name: str):
     if name == "bbh512mixed":
         mesh = nested_bbh_mesh()
         data = brill_lindquist(mesh, [(0.5, (5.0, 0.0, 0.0)), (0.5, (-5.0, 0.0, 0.0))])
-        return mesh, params_default(8, eta=2.0), data, cfl * mesh.dx(int(np.argmax(mesh.level))), 1
+        return mesh, params_default(8, eta=2.0), data, cfl * mesh.dx_min(), 1
     if name == "bbh4096x16":
         mesh = uniform_mesh((16, 16, 16), 16, 4, (-16.0,) * 3, (16.0,) * 3, BC_OUTFLOW)
         data = brill_lindquist(mesh, [(0.5, (5.0, 0.0, 0.0)), (0.5, (-5.0, 0.0, 0.0))])
