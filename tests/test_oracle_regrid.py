@@ -155,3 +155,26 @@ def test_transfer_matches_cross_level_ghost_fill(g):
             assert refined.level[kid] == 1 and tuple(refined.ilo[kid]) == (16, 8 * cy, 8 * cz)
             ghost = om.block_view(filled, old)[:, g:g + n, g:g + n, g + n:g + n + g]
             np.testing.assert_allclose(new[kid][:, :, :, 0:g], ghost, rtol=0, atol=1e-13)
+
+
+def test_prolongating_chi_through_a_puncture_overshoots_below_zero():
+    """Refining the block that holds a Brill-Lindquist puncture prolongates
+    chi = psi^-4 through its near-zero minimum: the (g+1)-point Lagrange
+    interpolant (g = 4) of the coarse values, all positive, is negative at
+    the fine cells next to the puncture, while the exact chi there is
+    positive.  This is why initial refinement around punctures sets the
+    data on the refined mesh instead of prolongating them."""
+    m0 = zi.uniform_mesh((2, 2, 2), N8, 4, (-1.0,) * 3, (1.0,) * 3, zi.BC_OUTFLOW)
+    p0 = (-0.5, -0.5, -0.5)                      # a cell corner of both levels, inside block 0
+    data = zi.brill_lindquist(m0, [(0.5, p0)])
+    assert min(float(b[0].min()) for b in data) > 0.0
+    flags = np.zeros(m0.nb)
+    flags[0] = 1
+    m1 = rg.plan(m0, flags, 1)
+    om = oracle.OracleMesh(m0)
+    new = rg.transfer(m0, om.scatter(data), m1)
+    exact = zi.brill_lindquist(m1, [(0.5, p0)])
+    fine = [b for b in range(m1.nb) if m1.level[b] == 1]
+    got_min = min(float(new[b][0].min()) for b in fine)
+    exact_min = min(float(exact[b][0].min()) for b in fine)
+    assert exact_min > 0.0 and got_min < 0.0, (got_min, exact_min)
