@@ -194,7 +194,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "halo-exchange design is described in DESIGN.md but not built.", file=sys.stderr)
+              "halo exchange is not built.", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2409_10383_amd as z4c

@@ -66,7 +66,7 @@ enum {
     Z4C_EDEVICE = -3,      /* a HIP call failed                              */
     Z4C_ESTATE = -4,       /* call out of order (e.g. not bound)             */
     Z4C_ENONFINITE = -5,   /* non-finite value found (finite check enabled)  */
-    Z4C_EUNSUPPORTED = -6  /* valid but not supported by this build          */
+    Z4C_EUNSUPPORTED = -6  /* valid but not supported by this library        */
 };
 
 enum { Z4C_REG_U = 0, Z4C_REG_S1 = 1, Z4C_REG_S2 = 2, Z4C_REG_A = 3 };
@@ -335,7 +335,7 @@ int z4c_tracker_get(struct z4c_pack *pack, double *pos, void *stream);
 /* ----------------------------------------------- learned refinement */
 /* The learned indicator predicts, per MeshBlock, the truncation error the
  * chi-based criteria of Sec. 3.3 stand in for, from cheap block features;
- * the plain dchi-max criterion stays as fallback and judge.  Features (16
+ * the plain dchi-max criterion stays as fallback and reference.  Features (16
  * per block, double): 0 max|d chi| 1 mean|d chi| 2 max|d alpha|
  * 3 mean|d alpha| 4 max|dd g~| 5 mean|dd g~| 6 min alpha 7 min chi
  * 8 max|Khat| 9 max|A~| 10 max|Theta| 11 max|Gamma~| 12 max|beta|
