@@ -16,6 +16,11 @@
       below zero, so initial refinement re-evaluates the data, as mesh
       generation does); each mesh and the unrefined one are evolved and
       their constraint norms reported.
+  python -m paper_2409_10383_amd.experiments blocksize [--steps 10]
+      the linear wave of Sec. 4.1 on 256^3 zones split into MeshBlocks of
+      16^3, 32^3, 64^3 (Table 1's size) and 128^3: zone-cycles per second of
+      each, FP64, 6th order, autotuned launch (Sec. 5 reports the gain of
+      larger MeshBlocks).
 
 Each prints one JSON object.  All arithmetic runs in libz4c.
 """
@@ -191,9 +196,48 @@ def adaptive(budget: int = 64, steps: int = 16, nvariants: int = 6, epochs: int 
                       "flag_overlap": overlap, "runs": runs}))
 
 
+def blocksize(steps: int = 10):
+    import torch
+    import paper_2409_10383_amd as z4c
+    import z4c_inputs as zi
+    p = zi.params_default(6)
+    rows = []
+    for n in (16, 32, 64, 128):
+        mesh, data = zi.linear_wave_pack(256 // n, n)
+        pk = z4c.Pack(mesh, p)
+        pk.upload(z4c.REG_U, data)
+        del data
+        chosen, _ = pk.autotune(reps=3)
+        dt = 0.25 * mesh.dx0
+        pk.rk4_step(dt, 2)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        pk.rk4_step(dt, steps)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        pk.profile(True)
+        pk.profile_read(reset=True)
+        pk.rk4_step(dt, 1)
+        st_ms, st_n, fill_ms, fill_n, _, _ = pk.profile_read(reset=True)
+        row = {"block": n, "blocks": int(mesh.nb), "zones": int(pk.zones),
+               "zcps": pk.zones * steps / (ms * 1e-3), "ms_per_step": ms / steps,
+               "stage_ms": st_ms / st_n, "fill_ms": fill_ms / max(fill_n, 1),
+               "tile": "x".join(str(v) for v in z4c.TILE_SHAPES[chosen // 2]),
+               "persistent": bool(chosen % 2)}
+        print(row, file=sys.stderr, flush=True)
+        rows.append(row)
+        del pk
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "linear wave, 256^3 zones, periodic unit cube", "fd_order": 6,
+                      "precision": "fp64", "steps": steps, "rows": rows}))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["precision", "learned", "adaptive"])
+    ap.add_argument("what", choices=["precision", "learned", "adaptive", "blocksize"])
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--budget", type=int, default=64)
     a = ap.parse_args(argv)
@@ -201,6 +245,8 @@ def main(argv=None):
         precision(a.steps or 100)
     elif a.what == "learned":
         learned()
+    elif a.what == "blocksize":
+        blocksize(a.steps or 10)
     else:
         adaptive(a.budget, a.steps or 16)
 

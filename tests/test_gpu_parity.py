@@ -180,6 +180,30 @@ def test_bl64x32_full_size_step_in_bench_launch_configuration():
     assert_parity(got, om.interiors(regs.U), what=f"step bl64x32 (variant {chosen})", mode="state")
 
 
+@pytest.mark.parametrize("n", [64, 128])
+def test_large_block_parity(n):
+    """One periodic block of 64^3 (Table 1's MeshBlock size) or 128^3
+    holding the linear wave plus perturbations of every field: RHS against
+    the oracle, and for 64^3 one RK4 step in the autotuner's launch."""
+    mesh, data = zi.linear_wave_pack(1, n)
+    data = zi.add_perturbation(mesh, data, seed=6, amp=1e-6, periodic_box=1.0)
+    p = zi.params_default(6)
+    _, rg = gpu_rhs(mesh, p, data)
+    assert_parity(rg, ora_rhs(mesh, p, data), what=f"rhs {n}^3")
+    if n == 64:
+        dt = 0.25 * mesh.dx0
+        pk = z().Pack(mesh, p)
+        pk.upload(z().REG_U, data)
+        chosen, _ = pk.autotune(reps=1)
+        pk.rk4_step(dt, 1)
+        torch.cuda.synchronize()
+        om = oracle.OracleMesh(mesh)
+        regs = oracle.Registers(om, data)
+        oracle.rk4_steps(regs, p, dt, 1)
+        assert_parity(pk.download(z().REG_U), om.interiors(regs.U), what=f"step 64^3 (variant {chosen})",
+                      mode="state")
+
+
 # tile counts that are not a multiple of 8 (the XCD-interleaved slot map has
 # a short last slice): one 24^3 block = 54 tiles, 3x3x1 blocks of 8^3 = 18
 RAGGED = {"one24": ((1, 1, 1), 24, (6.0, 6.0, 6.0)), "three_by_three8": ((3, 3, 1), 8, (6.0, 6.0, 2.0))}

@@ -298,6 +298,9 @@ def workload(name: str):
                 8th order, 5 ghosts, two BL punctures m = 0.5 at x = +-5.
     bbh4096x16  4096 blocks of 16^3 on [-16,16]^3 (dx = 0.125), 6th order,
                 two BL punctures m = 0.5 at x = +-5.
+    wave64x64   the linear gravitational wave of Sec. 4.1 (amplitude 1e-8,
+                along the diagonal of the periodic unit cube) on 64 blocks of
+                64^3 (256^3 zones), 6th order: Table 1's MeshBlock size.
     """
     cfl = 0.25
     if name == "periodic16":
@@ -316,11 +319,37 @@ def workload(name: str):
         mesh = nested_bbh_mesh()
         data = brill_lindquist(mesh, [(0.5, (5.0, 0.0, 0.0)), (0.5, (-5.0, 0.0, 0.0))])
         return mesh, params_default(8, eta=2.0), data, cfl * mesh.dx_min(), 1
+    if name == "wave64x64":
+        mesh, data = linear_wave_pack(4, 64)
+        return mesh, params_default(6), data, cfl * mesh.dx0, 1
     if name == "bbh4096x16":
         mesh = uniform_mesh((16, 16, 16), 16, 4, (-16.0,) * 3, (16.0,) * 3, BC_OUTFLOW)
         data = brill_lindquist(mesh, [(0.5, (5.0, 0.0, 0.0)), (0.5, (-5.0, 0.0, 0.0))])
         return mesh, params_default(6, eta=2.0), data, cfl * mesh.dx0, 1
     raise KeyError(name)
+
+
+def linear_wave_pack(nblk: int, n: int, amplitude: float = 1e-8):
+    """nblk^3 blocks of n^3 on the periodic unit cube holding the linear wave
+    travelling along the diagonal (analytic.linear_wave_diagonal) at t = 0.
+    The wave depends on the position only through x + y + z, so the fields
+    are evaluated once per value of the global index sum i + j + k (on the
+    diagonal point with that coordinate sum) and gathered into the blocks."""
+    from z4c_inputs import analytic
+    mesh = uniform_mesh((nblk,) * 3, n, 4, (0.0,) * 3, (1.0,) * 3, BC_PERIODIC)
+    fn = analytic.linear_wave_diagonal(amplitude, 1.0)
+    h = mesh.dx0
+    m = np.arange(3 * nblk * n - 2)
+    d = (m + 1.5) * h / 3.0                       # x = y = z with x + y + z = (m + 3/2) h
+    line = analytic.adm_to_z4c(fn, 0.0, d, d, d)  # (22, len(m))
+    out = []
+    for b in range(mesh.nb):
+        i = mesh.ilo[b, 0] + np.arange(n)
+        j = mesh.ilo[b, 1] + np.arange(n)
+        k = mesh.ilo[b, 2] + np.arange(n)
+        idx = k[:, None, None] + j[None, :, None] + i[None, None, :]
+        out.append(line[:, idx])
+    return mesh, out
 
 
 # ------------------------------------------------------- geodesic spheres
