@@ -151,8 +151,9 @@ typedef struct {
 
 /* Validate a pack description and build its host metadata (Sec. 3: Mesh,
  * MeshBlocks, MeshBlockPack).  Checks: fd_order in {4,6,8}; nghost >= N+1
- * (the Kreiss-Oliger and lopsided stencils reach N+1 cells); every n even
- * and >= nghost; blocks inside
+ * (the Kreiss-Oliger and lopsided stencils reach N+1 cells); nblocks >= 1;
+ * every n a multiple of 8 (the stage kernel's tiles), 8 <= n <= 512 and
+ * n >= nghost; levels 0..7; blocks inside
  * the domain, not overlapping, covering it; neighbouring levels differ by at
  * most one (the 2:1 rule, Sec. 3.3) with refinement-boundary stencils that
  * stay within one level.  Returns Z4C_EINVAL on any violation.  `blocks` is

@@ -93,7 +93,33 @@ def test_invalid_descriptions_rejected():
     assert _create(finer, p) == -1
     assert _create(fine, p) == 0
     assert _create(mesh, p, precision=3) == -1
+    for n in (4, 6, 12, 520):                                 # n: multiple of 8, 8..512
+        m5 = zi.uniform_mesh((1, 1, 1), n, 4, (0,) * 3, (1,) * 3, zi.BC_PERIODIC)
+        assert _create(m5, p) == -1, n
+    m6 = zi.uniform_mesh((1, 1, 1), 16, 4, (0,) * 3, (1,) * 3, zi.BC_PERIODIC)
+    m6.level[0] = 8                                           # level beyond 7
+    assert _create(m6, p) == -1
     h = C.c_void_p()                                          # empty pack
     assert z.lib().z4c_pack_create(C.byref(z.make_params(mesh, p)), z.make_blocks(mesh), 0,
                                    C.byref(h)) == -1
     assert _create(mesh, dict(p, terms=99)) == -1
+
+
+def test_layout_of_a_pack_beyond_int32_elements():
+    """512 blocks of 64^3 (6th order): a ghosted register of 4.2e9 elements
+    (33.6 GB) -- offsets and sizes are 64-bit throughout."""
+    mesh = zi.uniform_mesh((8, 8, 8), 64, 4, (0,) * 3, (1,) * 3, zi.BC_PERIODIC)
+    h = C.c_void_p()
+    assert z.lib().z4c_pack_create(C.byref(z.make_params(mesh, zi.params_default(6))),
+                                   z.make_blocks(mesh), mesh.nb, C.byref(h)) == 0
+    lay = z.Layout()
+    assert z.lib().z4c_pack_query(h, C.byref(lay)) == 0
+    E = 64 + 8
+    slab = (E ** 3 * 8 + 255) // 256 * 256 // 8               # elements per field, 256-byte rows
+    assert lay.reg_bytes[0] == 512 * 22 * slab * 8 > 2 ** 34
+    assert lay.reg_bytes[3] == 512 * 22 * 64 ** 3 * 8
+    assert lay.zones == 512 * 64 ** 3
+    so, io = C.c_int64(), C.c_int64()
+    assert z.lib().z4c_block_offset(h, 511, C.byref(so), C.byref(io)) == 0
+    assert so.value == 511 * 22 * slab > 2 ** 31 and io.value == 511 * 22 * 64 ** 3
+    z.lib().z4c_pack_destroy(h)
