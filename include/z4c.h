@@ -280,7 +280,10 @@ int z4c_regrid_plan(const struct z4c_pack *pack, const int8_t *flags, int32_t le
  * centres inside the owning child, the window of the coarse ghost fill).
  * Fills the ghosts of src_reg first (src's ghost cells are written).
  * Ghosts of dst_reg are left to the next fill.  Z4C_EINVAL if a dst block
- * is none of the three.  Enqueued on `stream`. */
+ * is none of the three.  Enqueued on `stream`.  The interpolants are not
+ * limited and no enforcement or floor is applied: prolongated through a
+ * puncture, chi can come out negative next to it, so a block holding a
+ * puncture should not be refined by transfer (set its data instead). */
 int z4c_regrid_transfer(struct z4c_pack *src, int32_t src_reg, struct z4c_pack *dst, int32_t dst_reg,
                         void *stream);
 
