@@ -308,7 +308,8 @@ int z4c_psi4(struct z4c_pack *pack, int32_t reg, const double origin[3], void *o
  * zone (device `src`, e.g. z4c_psi4's output) at npts points (device, x y z
  * per point): each point takes the finest block whose active cells contain
  * it and, per axis, the 4 cell centres nearest to it inside that block.
- * out (device): npts x ncomp doubles, NaN for points outside the mesh. */
+ * out (device): npts x ncomp doubles, NaN for points outside the mesh.
+ * npts = 0 does nothing (the pointers may then be NULL). */
 int z4c_interp(struct z4c_pack *pack, const void *src, int32_t ncomp, const double *pts, int32_t npts,
                double *out, void *stream);
 

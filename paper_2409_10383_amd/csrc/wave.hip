@@ -536,11 +536,12 @@ int z4c_psi4(z4c_pack* pk, int32_t reg, const double origin[3], void* out, void*
 int z4c_interp(z4c_pack* pk, const void* src, int32_t ncomp, const double* pts, int32_t npts, double* out,
                void* stream)
 {
-    if (!pk || !src || !pts || !out || ncomp < 1 || npts < 0) return Z4C_EINVAL;
+    if (!pk || ncomp < 1 || npts < 0) return Z4C_EINVAL;
     if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
     for (const z4c_block& B : pk->blk)
         if (B.n < 4) return fail(pk, Z4C_EUNSUPPORTED, "interpolation needs 4 cells per block");
-    if (npts == 0) return Z4C_OK;
+    if (npts == 0) return Z4C_OK;   // nothing to do; the pointers may be NULL
+    if (!src || !pts || !out) return fail(pk, Z4C_EINVAL, "NULL pointer");
     const PointArgs a = point_args(pk);
     hipLaunchKernelGGL(k_interp, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, as_stream(stream), a,
                        static_cast<const double*>(src), (int)ncomp, pts, (int)npts, out);
@@ -552,11 +553,12 @@ int z4c_interp(z4c_pack* pk, const void* src, int32_t ncomp, const double* pts, 
 int z4c_interp_state(z4c_pack* pk, int32_t reg, int32_t first, int32_t nfield, const double* pts, int32_t npts,
                      double* out, void* stream)
 {
-    if (!pk || !pts || !out || npts < 0) return Z4C_EINVAL;
+    if (!pk || npts < 0) return Z4C_EINVAL;
     if (reg < Z4C_REG_U || reg > Z4C_REG_S2) return fail(pk, Z4C_EINVAL, "bad register %d", reg);
     if (first < 0 || nfield < 1 || first + nfield > Z4C_NFIELDS) return fail(pk, Z4C_EINVAL, "bad fields");
     if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
-    if (npts == 0) return Z4C_OK;
+    if (npts == 0) return Z4C_OK;   // nothing to do; the pointers may be NULL
+    if (!pts || !out) return fail(pk, Z4C_EINVAL, "NULL pointer");
     const PointArgs a = point_args(pk);
     const dim3 grid((unsigned)((npts + 255) / 256));
     if (pk->p.precision == Z4C_FP64)

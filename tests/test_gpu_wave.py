@@ -155,3 +155,25 @@ def test_tracker_uniform_shift_is_exact_rk4(graph):
     for q in range(2):
         for a in range(3):
             assert abs(x[q, a] - (Rn @ np.array([beta0[a], x0[q, a]]))[1]) < 1e-14
+
+
+def test_empty_and_invalid_point_sets():
+    """Zero points: interpolation returns an empty result without a launch;
+    trackers: n = 0 stops tracking (a step still runs), more than
+    Z4C_MAXTRACK or a harmonic degree above 12 is rejected."""
+    mesh, data = bbh(1)
+    p = zi.params_default(6)
+    pk = z().Pack(mesh, p)
+    pk.upload(z().REG_U, data)
+    ps = pk.psi4(z().REG_U, ORIGIN)
+    assert pk.interp(ps, 2, np.zeros((0, 3))).shape == (0, 2)
+    assert pk.interp_state(z().REG_U, 0, 3, np.zeros((0, 3))).shape == (0, 3)
+    pk.tracker_set(np.array([[0.5, 0.5, 0.5]]))
+    pk.tracker_set(np.zeros((0, 3)))
+    pk.rk4_step(0.1 * mesh.dx0, 1)
+    assert pk.tracker_get().shape == (0, 3)
+    with pytest.raises(z().Z4cError):
+        pk.tracker_set(np.zeros((9, 3)))
+    P, w = zi.geodesic_sphere(2, 2.0, ORIGIN)
+    with pytest.raises(z().Z4cError):
+        z().swsh_project(np.ones(len(P), complex), P, w, ORIGIN, 13)
