@@ -70,9 +70,26 @@ def cpu_baseline(workload):
     t0 = time.perf_counter()
     oracle.rk4_steps(regs, p, dt, nsteps)
     sec = time.perf_counter() - t0
-    return {"value": mesh.zones() * nsteps / sec, "unit": "zone-cycles/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nsteps} RK4 steps of 8 blocks of {n}^3 (dx={h}, order {p['fd_order']}, "
-                      f"Brill-Lindquist) on one host core, {sec:.1f} s"}
+    out = {"value": mesh.zones() * nsteps / sec, "unit": "zone-cycles/s", "cores": 1, "kind": "oracle",
+           "sample": f"{nsteps} RK4 steps of 8 blocks of {n}^3 (dx={h}, order {p['fd_order']}, "
+                     f"Brill-Lindquist) on one host core, {sec:.1f} s"}
+    # all usable host cores (at most 16, one GPU's share): the same sample,
+    # one independent copy per thread (the oracle's C calls release the GIL)
+    import concurrent.futures as cf
+    ncores = max(1, min(len(os.sched_getaffinity(0)), 16))
+
+    def one(_):
+        r = oracle.Registers(om, data)
+        oracle.rk4_steps(r, p, dt, 1)
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=ncores) as ex:
+        list(ex.map(one, range(ncores)))
+    sec_all = time.perf_counter() - t0
+    out["all_cores"] = {"value": ncores * mesh.zones() / sec_all, "cores": ncores,
+                        "sample": f"one RK4 step of the same 8 blocks per thread, {ncores} threads, "
+                                  f"{sec_all:.1f} s"}
+    return out
 
 
 def _pmc_rows(d, counter):
@@ -135,6 +152,28 @@ def summarize_pmc(args):
     with open(path, "w") as f:
         json.dump(doc, f, indent=1)
     print(json.dumps({key: out}))
+
+
+def copy_bandwidth():
+    """Achievable HBM bandwidth: a timed 2 GiB device-to-device copy
+    (2 GiB read + 2 GiB written), best of 5."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * (1 << 31) / (best * 1e-3) / 1e9
 
 
 def copy_calibration():
@@ -269,8 +308,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_stage (fused RHS + RK4 stage)",
                      "avg_launch_ms": st_ms / st_n, "launches": int(st_n),
+                     "achievable_copy_GBs": None,
                      "ghost_fill_avg_ms": (fill_ms / fill_n) if fill_n else None},
     }
+    out["roofline"]["achievable_copy_GBs"] = copy_bandwidth()
     if args.copy_calibration:
         copy_calibration()
     if not args.no_extras:
