@@ -82,7 +82,7 @@ enum {
 };
 enum {
     Z4C_FLAG_ENFORCE = 1,       /* det g~ = 1, tr A~ = 0, floors after writes */
-    Z4C_FLAG_CHECK_FINITE = 2,  /* reserved                                 */
+    Z4C_FLAG_CHECK_FINITE = 2,  /* z4c_rk4_step checks U for non-finite values */
     Z4C_FLAG_GRAPH = 4          /* z4c_rk4_step replays a captured hipGraph  */
 };
 
@@ -213,7 +213,10 @@ int z4c_rk4_stage(struct z4c_pack *pack, int32_t stage, double dt, void *stream)
 
 /* nsteps full RK4 steps of U (four stages each).  With Z4C_FLAG_GRAPH and a
  * non-NULL stream, the four stages (ghost fills included) are captured once
- * into a hipGraph per (dt, stream) and replayed for every step. */
+ * into a hipGraph per (dt, stream) and replayed for every step.  With
+ * Z4C_FLAG_CHECK_FINITE, after the steps every value of U's active cells is
+ * checked (one read of U, then the stream is synchronised); Z4C_ENONFINITE
+ * if any is NaN or infinite (U is left as computed). */
 int z4c_rk4_step(struct z4c_pack *pack, double dt, int32_t nsteps, void *stream);
 
 /* Launch configuration of the fused stage kernel (batching, Sec. 3:

@@ -153,7 +153,8 @@ def make_params(mesh, p: dict, precision: int = FP64) -> Params:
     for k in ("ko_sigma", "kappa1", "kappa2", "eta", "mu_S", "chi_floor", "alpha_floor"):
         setattr(q, k, float(p[k]))
     q.terms = int(p.get("terms", TERM_ALL))
-    q.flags = (FLAG_ENFORCE if int(p.get("enforce", 1)) else 0) | (FLAG_GRAPH if p.get("graph") else 0)
+    q.flags = ((FLAG_ENFORCE if int(p.get("enforce", 1)) else 0) | (FLAG_GRAPH if p.get("graph") else 0)
+               | (FLAG_CHECK_FINITE if p.get("check_finite") else 0))
     return q
 
 

@@ -610,6 +610,7 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
     pk->ws_vnbr = o;   o = align256(o + sizeof(int64_t) * 27 * nblocks);
     pk->ws_vmask = o;  o = align256(o + sizeof(uint32_t) * nblocks);
     pk->ws_track = o;  o = align256(o + sizeof(double) * 9 * Z4C_MAXTRACK);
+    pk->ws_flag = o;   o = align256(o + sizeof(int32_t));
     pk->ws_total = o;
     pk->part_host.resize(16 * pk->work.size());
     pk->first_work.assign(nblocks + 1, 0);
@@ -847,7 +848,33 @@ int z4c_rk4_stage(z4c_pack* pk, int32_t stage, double dt, void* stream)
     return Z4C_OK;
 }
 
+// with Z4C_FLAG_CHECK_FINITE: every value of U's active cells finite?
+static int check_finite(z4c_pack* pk, hipStream_t s)
+{
+    FiniteArgs a;
+    a.src = pk->reg[Z4C_REG_U];
+    a.blocks = reinterpret_cast<const BlockDev*>(pk->ws + pk->ws_blocks);
+    a.work = reinterpret_cast<const WorkItem*>(pk->ws + pk->ws_work);
+    a.flag = reinterpret_cast<int32_t*>(pk->ws + pk->ws_flag);
+    a.g = pk->p.nghost;
+    int32_t bad = 0;
+    hipError_t e = launch_check_finite(pk->p.precision, a, (int)pk->work.size(), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, a.flag, sizeof(bad), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "finite check: %s", hipGetErrorString(e));
+    return bad ? fail(pk, Z4C_ENONFINITE, "non-finite value in U after the step") : Z4C_OK;
+}
+
+static int rk4_steps(z4c_pack* pk, double dt, int32_t nsteps, void* stream);
+
 int z4c_rk4_step(z4c_pack* pk, double dt, int32_t nsteps, void* stream)
+{
+    const int rc = rk4_steps(pk, dt, nsteps, stream);
+    if (rc || !(pk->p.flags & Z4C_FLAG_CHECK_FINITE) || nsteps == 0) return rc;
+    return check_finite(pk, as_stream(stream));
+}
+
+static int rk4_steps(z4c_pack* pk, double dt, int32_t nsteps, void* stream)
 {
     if (!pk) return Z4C_EINVAL;
     if (nsteps < 0) return fail(pk, Z4C_EINVAL, "negative nsteps");

@@ -8,6 +8,41 @@ namespace z4c {
 
 constexpr int NPART = 8;
 
+// any non-finite value among the 22 fields of the active cells of a tile
+// sets the flag (cleared by k_clear_flag, launched just before on the same
+// stream)
+template <class T>
+__global__ __launch_bounds__(256) void k_check_finite(const FiniteArgs a)
+{
+    const WorkItem w = a.work[blockIdx.x];
+    const BlockDev B = a.blocks[w.block];
+    const int t = threadIdx.x;
+    const int li = t % w.ni, lj = (t / w.ni) % w.nj, lk = t / (w.ni * w.nj);
+    if (lk >= w.nk) return;
+    const int g = a.g, E = B.E;
+    const int64_t cc = ((int64_t)(w.k0 + lk + g) * E + (w.j0 + lj + g)) * E + (w.i0 + li + g);
+    const T* p = (const T*)a.src + B.off + cc;
+    bool bad = false;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) bad |= !__builtin_isfinite((double)p[f * B.slab]);
+    if (bad) atomicOr(a.flag, 1);
+}
+
+__global__ void k_clear_flag(int32_t* flag)
+{
+    if (threadIdx.x == 0) *flag = 0;
+}
+
+hipError_t launch_check_finite(int prec, const FiniteArgs& a, int nwork, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, s, a.flag);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_check_finite<double>, dim3((unsigned)nwork), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_check_finite<float>, dim3((unsigned)nwork), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 // fixed-order workgroup reduction of 256 values (sum or max / min)
 template <int OP>
 __device__ double wg_reduce(double x, double* sh)

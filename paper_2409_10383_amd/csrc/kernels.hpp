@@ -98,6 +98,15 @@ struct DiagArgs {
     int32_t g;
 };
 
+// finite-value check of a state register's active cells
+struct FiniteArgs {
+    const void* src;
+    const BlockDev* blocks;
+    const WorkItem* work;
+    int32_t* flag;            // set to 1 where a value is not finite
+    int32_t g;
+};
+
 struct FeatArgs {
     const void* src;
     const BlockDev* blocks;
@@ -140,6 +149,7 @@ hipError_t launch_stage(int N, int prec, int variant, const StageArgs& a, int gr
 int stage_occupancy(int N, int prec, int variant);
 hipError_t launch_fill(int prec, const FillArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_diag(int N, int prec, const DiagArgs& a, int nwork, hipStream_t s);
+hipError_t launch_check_finite(int prec, const FiniteArgs& a, int nwork, hipStream_t s);
 hipError_t launch_xlevel(int prec, const XlevelArgs& a, hipStream_t s);
 hipError_t launch_regrid(int prec, const RegridArgs& a, int nblocks, int maxn, hipStream_t s);
 

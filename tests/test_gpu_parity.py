@@ -233,3 +233,28 @@ def test_ragged_tile_count_parity(shape, persistent):
     oracle.rk4_steps(regs, p, dt, 1)
     torch.cuda.synchronize()
     assert_parity(pk.download(0), om.interiors(regs.U), what=f"step {shape}", mode="state")
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_check_finite_flag(graph):
+    """Z4C_FLAG_CHECK_FINITE: a NaN in one active cell of the input makes
+    z4c_rk4_step return Z4C_ENONFINITE; finite data passes, and without the
+    flag the same NaN goes unreported."""
+    mesh, p, data = small_bl(6)
+    dt = 0.25 * mesh.dx0
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        pk = z().Pack(mesh, dict(p, check_finite=1, graph=int(graph)))
+        pk.upload(z().REG_U, data)
+        pk.rk4_step(dt, 2, stream=s)
+        bad = [b.copy() for b in data]
+        bad[3][7, 2, 5, 1] = np.nan
+        pk.upload(z().REG_U, bad)
+        with pytest.raises(z().Z4cError) as err:
+            pk.rk4_step(dt, 1, stream=s)
+        assert err.value.code == -5
+        quiet = z().Pack(mesh, p)
+        quiet.upload(z().REG_U, bad)
+        quiet.rk4_step(dt, 1, stream=s)
+        torch.cuda.synchronize()
+        assert not np.isfinite(quiet.download(z().REG_U)[3]).all()
