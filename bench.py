@@ -311,9 +311,11 @@ def main():
                      "achievable_copy_GBs": None,
                      "ghost_fill_avg_ms": (fill_ms / fill_n) if fill_n else None},
     }
-    out["roofline"]["achievable_copy_GBs"] = copy_bandwidth()
     if args.copy_calibration:
+        # counter runs: the 1 GiB copy must be the largest copy of the run
         copy_calibration()
+    else:
+        out["roofline"]["achievable_copy_GBs"] = copy_bandwidth()
     if not args.no_extras:
         del pack
         torch.cuda.empty_cache()
