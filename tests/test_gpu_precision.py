@@ -101,3 +101,46 @@ def test_fp32_hamiltonian_within_twice_fp64():
     print("H_L2 fp32/fp64: full", r_full, "excised", r_exc)
     assert r_full <= 2.0
     assert np.isfinite(r_exc)
+
+
+def _two_level(g):
+    base = zi.uniform_mesh((4, 4, 4), 8, g, (0.0,) * 3, (32.0,) * 3, zi.BC_OUTFLOW)
+    return zi.refine_blocks(base, zi.blocks_in_box(base, (8.0,) * 3, (24.0,) * 3))
+
+
+@pytest.mark.parametrize("order", [6, 8])
+def test_fp32_cross_level_fill_and_rhs(order):
+    """FP32 storage on a two-level mesh: every ghost cell (same-level copies,
+    restriction and prolongation with double weights and a float32 store)
+    against the oracle's fill of the same rounded data, within one float32
+    rounding of the value plus four of the field's scale: restricted coarse
+    images and shadow values are themselves stored in float32, and the
+    prolongation weights (sum of |w| per axis about 1.3, cubed) carry their
+    rounding into the fine ghosts; the RHS across the refinement boundary
+    within the FP32 bound at the finest spacing."""
+    from z4c_inputs import analytic as an
+    mesh = _two_level(order // 2 + 1)
+    fn = an.kerr_schild(1.0, centre=(16.3, 15.8, 16.1))
+    data = [an.adm_to_z4c(fn, 0.0, *mesh.grid(b)) for b in range(mesh.nb)]
+    data = zi.add_perturbation(mesh, data, seed=3, amp=1e-4)
+    data = [d.astype(np.float32).astype(np.float64) for d in data]
+    p = zi.params_default(order)
+    pk = z().Pack(mesh, p, z().FP32_MIXED)
+    pk.upload(z().REG_U, data)
+    pk.fill_ghosts()
+    got = pk.download(z().REG_U, ghosted=True)
+    om = oracle.OracleMesh(mesh)
+    u = om.scatter(data)
+    oracle.fill_ghosts(om, u)
+    want = [om.block_view(u, b) for b in range(mesh.nb)]
+    fmax = np.max([np.abs(w).reshape(22, -1).max(1) for w in want], axis=0)
+    for b, (g_, w_) in enumerate(zip(got, want)):
+        tol = U32 * (2.0 * np.abs(w_) + 4.0 * fmax[:, None, None, None])
+        assert np.all(np.abs(g_ - w_) <= tol), (b, float(np.max((np.abs(g_ - w_) - tol)
+                                                                / fmax[:, None, None, None])))
+    rg = pk.split_interior(pk.rhs())
+    ro = oracle.rhs(om, p, om.scatter(data))
+    bound = rhs_bound(order, mesh.dx_min(), ro, data)
+    err = np.max([np.abs(g - o).reshape(22, -1).max(1) for g, o in zip(rg, ro)], axis=0)
+    assert np.all(err <= bound), [(f, err[f], bound[f]) for f in range(22) if err[f] > bound[f]]
+    print(order, "max err/bound:", float((err / bound).max()))
