@@ -144,3 +144,27 @@ def test_fp32_cross_level_fill_and_rhs(order):
     err = np.max([np.abs(g - o).reshape(22, -1).max(1) for g, o in zip(rg, ro)], axis=0)
     assert np.all(err <= bound), [(f, err[f], bound[f]) for f in range(22) if err[f] > bound[f]]
     print(order, "max err/bound:", float((err / bound).max()))
+
+
+def test_fp32_storage_constraints_and_interpolation_in_double():
+    """Constraint monitors and state interpolation read FP32 storage but
+    compute in double, so on data already rounded to float32 they equal the
+    oracle's double results on the same data to the FP64 bar."""
+    from _parity import assert_parity
+    from oracle import extract as ex
+    mesh = zi.uniform_mesh((2, 2, 2), 8, 4, (-4.0,) * 3, (4.0,) * 3, zi.BC_OUTFLOW)
+    data = zi.brill_lindquist(mesh, [(1.0, (0.1, -0.2, 0.05))])
+    data = zi.add_perturbation(mesh, data, seed=8, amp=1e-4)
+    data = [d.astype(np.float32).astype(np.float64) for d in data]
+    p = zi.params_default(6)
+    pk = z().Pack(mesh, p, z().FP32_MIXED)
+    pk.upload(z().REG_U, data)
+    cz, norms = pk.constraints(z().REG_U, exclude=[(0.1, -0.2, 0.05)], r_exc=1.0)
+    om = oracle.OracleMesh(mesh)
+    co, no = oracle.constraints(om, p, om.scatter(data), exclude=[(0.1, -0.2, 0.05)], r_exc=1.0)
+    assert_parity(pk.split_interior(cz, 8), co, what="constraints, FP32 storage")
+    np.testing.assert_allclose(norms, no, rtol=1e-12, atol=0)
+    pts = np.random.default_rng(4).uniform(-3.9, 3.9, size=(300, 3))
+    got = pk.interp_state(z().REG_U, 18, 4, pts)
+    want = ex.interpolate(mesh, [b[18:22] for b in data], pts)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
