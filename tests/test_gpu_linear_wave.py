@@ -105,3 +105,33 @@ def test_refined_corner_interface_order():
     print("L1_RMS refined corner", ref, "rates", rates, "uniform 32^3", uni)
     assert all(r > 3.7 for r in rates), (ref, rates)
     assert ref[1] < 3.0 * uni, (ref[1], uni)
+
+
+def evolve_amplitude(n, A, cfl=0.0625):
+    fn = an.linear_wave_diagonal(A, 1.0)
+    mesh = cube(n)
+    data = [an.adm_to_z4c(fn, 0.0, *mesh.grid(b)) for b in range(mesh.nb)]
+    nst = int(math.ceil(fn.period / (cfl * mesh.dx_min())))
+    pk = z().Pack(mesh, zi.params_default(6))
+    pk.upload(z().REG_U, data)
+    pk.rk4_step(fn.period / nst, nst)
+    torch.cuda.synchronize()
+    return l1_rms(mesh, pk.download(z().REG_U), data)
+
+
+def test_error_plateau_is_quadratic_in_amplitude():
+    """Sec. 4.1: above the truncation error the one-period error plateaus,
+    quadratically in the wave amplitude with a coefficient of order 10
+    (tests/golden/paper_parameters.json): e = c A^2 with c independent of A
+    and of the resolution."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_parameters.json")) as f:
+        g = json.load(f)["linear_wave_plateau"]
+    e = {(n, A): evolve_amplitude(n, A) for n in (16, 24) for A in (1e-4, 1e-3)}
+    c = {k: v / k[1] ** g["scaling_power"] for k, v in e.items()}
+    print("plateau coefficients", c)
+    ref = c[(16, 1e-3)]
+    assert all(abs(v / ref - 1.0) < 0.01 for v in c.values()), c
+    order = g["coefficient_order_of_magnitude"]
+    assert order / 10 <= ref <= order * 10, ref
