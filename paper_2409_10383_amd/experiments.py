@@ -36,6 +36,7 @@ def precision(steps: int):
     import paper_2409_10383_amd as z4c
     import z4c_inputs as zi
     mesh, p, data, dt, _ = zi.workload("bl512x32")
+    print("precision: data ready", file=sys.stderr, flush=True)
     res = {}
     states = {}
     for prec, name in ((z4c.FP64, "fp64"), (z4c.FP32_MIXED, "fp32")):
@@ -53,8 +54,27 @@ def precision(steps: int):
         res[name] = {"zcps": pk.zones * steps / (ms * 1e-3), "H_L2": nf[0], "H_L2_excised": ne[0],
                      "M_L2": nf[2]}
         states[name] = pk.download(z4c.REG_U)
+        print(f"precision: {name} run done", file=sys.stderr, flush=True)
         del pk
         torch.cuda.empty_cache()
+    # a-priori bound of the FP32-storage error per field after n steps:
+    #   storage rounding  n u32 max|f|
+    # + derivative rounding  n dt K u32 (max|rhs_f| + S W2 / h^2)
+    # (u32 = 2^-24; S = the largest |value| of the O(1) fields; W2 = sum of
+    # |w| of the second-derivative stencil; K = 64 terms per right-hand side;
+    # the FP64 accumulation is negligible), with max|f| and max|rhs_f| from
+    # the FP64 run's initial state
+    u32 = 2.0 ** -24
+    pk = z4c.Pack(mesh, p, z4c.FP64)
+    pk.upload(z4c.REG_U, data)
+    pk.fill_ghosts()
+    rhs0 = pk.split_interior(pk.rhs())
+    del pk
+    torch.cuda.empty_cache()
+    S = max(float(np.abs(d[[0, 1, 4, 6, 18]]).max()) for d in data)
+    w2 = float(np.sum(np.abs(z4c.stencil_weights(p["fd_order"])[1][1:]))) * 2 + \
+        abs(float(z4c.stencil_weights(p["fd_order"])[1][0]))
+    h = mesh.dx0
     err = {}
     for f in range(22):
         num2 = den2 = numi = deni = 0.0
@@ -64,8 +84,12 @@ def precision(steps: int):
             den2 += float(np.sum(b[f] * b[f]))
             numi = max(numi, float(np.abs(d).max()))
             deni = max(deni, float(np.abs(b[f]).max()))
+        fmax = max(float(np.abs(b[f]).max()) for b in data)
+        rmax = max(float(np.abs(r[f]).max()) for r in rhs0)
+        bound = steps * u32 * fmax + steps * dt * 64.0 * u32 * (rmax + S * w2 / h ** 2)
         err[zi.FIELDS[f]] = {"rel_L2": (num2 / max(den2, 1e-300)) ** 0.5,
-                             "rel_Linf": numi / max(deni, 1e-300)}
+                             "rel_Linf": numi / max(deni, 1e-300),
+                             "Linf": numi, "apriori_bound": bound, "Linf_over_bound": numi / bound}
     out = {"workload": "bl512x32", "steps": steps, "dt": dt, "runs": res, "errors": err,
            "H_L2_ratio": res["fp32"]["H_L2"] / res["fp64"]["H_L2"],
            "H_L2_excised_ratio": res["fp32"]["H_L2_excised"] / res["fp64"]["H_L2_excised"]}
