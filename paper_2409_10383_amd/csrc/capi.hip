@@ -374,12 +374,17 @@ int build_xlevel(z4c_pack* pk)
 // y and z alone: across the x face it reads that neighbour's own x ghosts,
 // which stay real.  Lanes that are not 16-byte aligned at all (ghost depth
 // and halo of different parity) copy per half cell from the block itself.
+// Outflow boundaries: where every nonzero component of a direction with
+// dx = 0 leaves the domain, the outflow ghost is the block's own active cell
+// with y and z clamped to its active range (the block spans the domain edge),
+// so the stage reads that cell directly and the fill skips the direction too.
 void build_virtual_halos(z4c_pack* pk)
 {
     const int nb = (int)pk->blk.size();
     const int g = pk->p.nghost, R = pk->p.fd_order / 2 + 1;
     pk->vnbr.assign((size_t)27 * nb, 0);
     pk->vmask.assign(nb, 0u);
+    pk->cmask.assign(nb, 0u);
     pk->virt_x = 1;
     for (int b = 0; b < nb; ++b)
         for (int i = 0; i < 27; ++i) pk->vnbr[27 * b + i] = pk->bdev[b].off;
@@ -399,8 +404,22 @@ void build_virtual_halos(z4c_pack* pk)
             for (int dy = -1; dy <= 1; ++dy)
                 for (int dx = -1; dx <= 1; ++dx) {
                     if (!dx && !dy && !dz) continue;
-                    if (dx && !pk->virt_x) continue;
                     const int dd[3] = {dx, dy, dz};
+                    if (!dx && pk->p.bc == Z4C_BC_OUTFLOW) {
+                        bool all_out = true;
+                        for (int a = 1; a < 3; ++a) {
+                            const int64_t N = (int64_t)pk->p.nroot[a] << B.level;
+                            const int64_t Ja = (int64_t)B.ilo[a] + (int64_t)dd[a] * B.n;
+                            if (dd[a] && Ja >= 0 && Ja < N) all_out = false;
+                        }
+                        if (all_out) {
+                            const int idx = (dz + 1) * 9 + (dy + 1) * 3 + 1;
+                            pk->cmask[b] |= 1u << idx;
+                            pk->vmask[b] |= 1u << idx;
+                            continue;
+                        }
+                    }
+                    if (dx && !pk->virt_x) continue;
                     int64_t J[3];
                     bool inside = true;
                     for (int a = 0; a < 3; ++a) {
@@ -609,6 +628,7 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
     pk->ws_regrid = o; o = align256(o + sizeof(RegridDesc) * nblocks);
     pk->ws_vnbr = o;   o = align256(o + sizeof(int64_t) * 27 * nblocks);
     pk->ws_vmask = o;  o = align256(o + sizeof(uint32_t) * nblocks);
+    pk->ws_cmask = o;  o = align256(o + sizeof(uint32_t) * nblocks);
     pk->ws_track = o;  o = align256(o + sizeof(double) * 9 * Z4C_MAXTRACK);
     pk->ws_flag = o;   o = align256(o + sizeof(int32_t));
     pk->ws_total = o;
@@ -678,6 +698,9 @@ int z4c_pack_bind(z4c_pack* pk, void* const regs[Z4C_NREG], void* workspace, siz
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ws + pk->ws_vmask, pk->vmask.data(), sizeof(uint32_t) * pk->vmask.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + pk->ws_cmask, pk->cmask.data(), sizeof(uint32_t) * pk->cmask.size(),
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !pk->islice.empty())
         e = hipMemcpyAsync(ws + pk->ws_islice, pk->islice.data(), sizeof(ImageSlice) * pk->islice.size(),
@@ -802,6 +825,7 @@ static StageArgs stage_args(z4c_pack* pk)
     a.A = static_cast<double*>(pk->reg[Z4C_REG_A]);
     a.U = pk->reg[Z4C_REG_U];
     a.vnbr = reinterpret_cast<const int64_t*>(pk->ws + pk->ws_vnbr);
+    a.cmask = reinterpret_cast<const uint32_t*>(pk->ws + pk->ws_cmask);
     a.virt_x = pk->virt_x;
     return a;
 }

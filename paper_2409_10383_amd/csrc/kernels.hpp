@@ -14,6 +14,7 @@ struct StageArgs {
     const BlockDev* blocks;
     const WorkItem* work;
     const int64_t* vnbr;      // per block, 27 direction offsets of the staged halo
+    const uint32_t* cmask;    // per block, directions read clamped (outflow)
     ParamsDev P;
     double dt;
     int32_t stage;            // 1..4, 0 = RHS only

@@ -34,7 +34,9 @@ struct z4c_pack {
     size_t ws_xfer = 0, ws_prol = 0, ws_pgrp = 0, ws_islice = 0, ws_w = 0, ws_shadow = 0, ws_image = 0;
     size_t ws_regrid = 0, ws_vnbr = 0, ws_vmask = 0;
     std::vector<int64_t> vnbr;    // virtual halos: 27 offsets per block
-    std::vector<uint32_t> vmask;  // virtual-halo directions per block
+    std::vector<uint32_t> vmask;  // directions the stage path's fill skips, per block
+    std::vector<uint32_t> cmask;  // of those, the clamped outflow directions
+    size_t ws_cmask = 0;
     int virt_x = 1;               // 0: only directions with dx = 0 are virtual
     // puncture tracker: device state (x, k_prev, acc) per puncture in the workspace
     int ntrack = 0;

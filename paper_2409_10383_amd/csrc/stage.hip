@@ -288,6 +288,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     // where the pack provides a virtual halo for that direction (the offset
     // table then points the block's ghosted index at the neighbour's cells)
     const int64_t* vn = a.vnbr + (int64_t)w.block * 27;
+    // clamped outflow directions read the block's own active cells, with the
+    // y and z of the staged cell clamped to the active range
+    const uint32_t cm = a.cmask[w.block];
     int soff[NRS];
 #pragma unroll
     for (int r = 0; r < NRS; ++r) {
@@ -296,7 +299,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
         const int lx = x + w.i0 - R, ly = y + w.j0 - R, lz = z + w.k0 - R;
         const int dir = ((lz < 0 ? 0 : (lz >= n ? 2 : 1)) * 3 + (ly < 0 ? 0 : (ly >= n ? 2 : 1))) * 3 +
                         (a.virt_x ? (lx < 0 ? 0 : (lx >= n ? 2 : 1)) : 1);
-        soff[r] = (int)(vn[dir] - B.off) + ((lz + g) * E + (ly + g)) * E + (lx + g);
+        const bool clamp = (cm >> dir) & 1u;
+        const int cy = clamp ? (ly < 0 ? 0 : (ly >= n ? n - 1 : ly)) : ly;
+        const int cz = clamp ? (lz < 0 ? 0 : (lz >= n ? n - 1 : lz)) : lz;
+        soff[r] = (int)(vn[dir] - B.off) + ((cz + g) * E + (cy + g)) * E + (lx + g);
     }
     auto issue = [&](int f, C* buf) {
         if (wide) {
