@@ -454,7 +454,8 @@ struct ProfScope {
     ProfScope(z4c_pack* p, hipStream_t st, int k) : pk(p), s(st), kind(k)
     {
         if (!pk->prof) return;
-        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+        if (hipEventCreate(&a) != hipSuccess) { a = nullptr; return; }
+        if (hipEventCreate(&b) != hipSuccess) { hipEventDestroy(a); a = b = nullptr; return; }
         hipEventRecord(a, s);
     }
     ~ProfScope()
@@ -745,17 +746,19 @@ int z4c_profile(z4c_pack* pk, int32_t enable)
 int z4c_profile_read(z4c_pack* pk, double* out, int32_t reset)
 {
     if (!pk || !out) return Z4C_EINVAL;
+    hipError_t r = hipSuccess;
     for (auto& e : pk->ev) {
         float ms = 0.f;
-        hipError_t r = hipEventSynchronize(e.b);
+        if (r == hipSuccess) r = hipEventSynchronize(e.b);
         if (r == hipSuccess) r = hipEventElapsedTime(&ms, e.a, e.b);
         hipEventDestroy(e.a);
         hipEventDestroy(e.b);
-        if (r != hipSuccess) { pk->ev.clear(); return fail(pk, Z4C_EDEVICE, "profile: %s", hipGetErrorString(r)); }
+        if (r != hipSuccess) continue;  // keep destroying the rest
         pk->prof_acc[2 * e.kind] += ms;
         pk->prof_acc[2 * e.kind + 1] += 1.0;
     }
     pk->ev.clear();
+    if (r != hipSuccess) return fail(pk, Z4C_EDEVICE, "profile: %s", hipGetErrorString(r));
     for (int q = 0; q < 6; ++q) out[q] = pk->prof_acc[q];
     if (reset)
         for (int q = 0; q < 6; ++q) pk->prof_acc[q] = 0.0;
@@ -988,8 +991,11 @@ int z4c_autotune(z4c_pack* pk, int32_t reps, double* times_ms, int32_t* chosen, 
             rc = z4c_set_variant(pk, v, per, stream);
             if (rc) return rc;
             hipEvent_t e0, e1;
-            if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+            if (hipEventCreate(&e0) != hipSuccess) return fail(pk, Z4C_EDEVICE, "autotune events");
+            if (hipEventCreate(&e1) != hipSuccess) {
+                hipEventDestroy(e0);
                 return fail(pk, Z4C_EDEVICE, "autotune events");
+            }
             // RK stage 1 with dt = 0: writes only S1 and the accumulator
             rc = z4c_rk4_stage(pk, 1, 0.0, stream);  // warm-up
             hipEventRecord(e0, s);
