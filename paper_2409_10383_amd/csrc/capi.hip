@@ -445,6 +445,17 @@ void build_virtual_halos(z4c_pack* pk)
     }
 }
 
+// side stream and its fork/join events (multi-level packs)
+void release_side(z4c_pack* pk)
+{
+    if (pk->side) hipStreamSynchronize(pk->side);
+    if (pk->fork_ev) hipEventDestroy(pk->fork_ev);
+    if (pk->join_ev) hipEventDestroy(pk->join_ev);
+    if (pk->side) hipStreamDestroy(pk->side);
+    pk->side = nullptr;
+    pk->fork_ev = pk->join_ev = nullptr;
+}
+
 // bracket a launch with events when profiling is on (kind 0 stage, 1 fill)
 struct ProfScope {
     z4c_pack* pk;
@@ -717,6 +728,16 @@ int z4c_pack_bind(z4c_pack* pk, void* const regs[Z4C_NREG], void* workspace, siz
         e = hipMemcpyAsync(ws + pk->ws_w, pk->wtab.data(), sizeof(double) * 80, hipMemcpyHostToDevice, s);
     }
     if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "table upload: %s", hipGetErrorString(e));
+    if (pk->multilevel && !pk->side) {
+        // default priority, not synchronised with the legacy null stream
+        e = hipStreamCreateWithFlags(&pk->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&pk->fork_ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&pk->join_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            release_side(pk);
+            return fail(pk, Z4C_EDEVICE, "side stream: %s", hipGetErrorString(e));
+        }
+    }
     for (int r = 0; r < Z4C_NREG; ++r) pk->reg[r] = regs[r];
     pk->ws = ws;
     pk->bound = true;
@@ -729,6 +750,7 @@ void z4c_pack_destroy(z4c_pack* pk)
     if (!pk) return;
     if (pk->gexec) hipGraphExecDestroy(pk->gexec);
     if (pk->graph) hipGraphDestroy(pk->graph);
+    release_side(pk);
     for (auto& e : pk->ev) {
         hipEventDestroy(e.a);
         hipEventDestroy(e.b);
@@ -783,7 +805,20 @@ static int fill_impl(z4c_pack* pk, int32_t reg, void* stream, bool virt)
     for (int d = 0; d < 3; ++d) a.nroot[d] = pk->p.nroot[d];
     a.maxghost = pk->maxghost;
     ProfScope ps(pk, as_stream(stream), 1);
-    hipError_t e = launch_fill(pk->p.precision, a, (int)pk->blk.size(), as_stream(stream));
+    const hipStream_t s = as_stream(stream);
+    // the same-level copies and the cross-level chain (restriction, transfers,
+    // prolongation) read only active cells and write disjoint ghost cells, so
+    // on multi-level packs the former runs on the side stream beside the latter
+    const bool fork = pk->multilevel && pk->side;
+    hipError_t e = hipSuccess;
+    if (fork) {
+        e = hipEventRecord(pk->fork_ev, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(pk->side, pk->fork_ev, 0);
+        if (e == hipSuccess) e = launch_fill(pk->p.precision, a, (int)pk->blk.size(), pk->side);
+        if (e == hipSuccess) e = hipEventRecord(pk->join_ev, pk->side);
+    } else {
+        e = launch_fill(pk->p.precision, a, (int)pk->blk.size(), s);
+    }
     if (e == hipSuccess && pk->multilevel) {
         XlevelArgs x;
         x.reg = pk->reg[reg];
@@ -801,7 +836,12 @@ static int fill_impl(z4c_pack* pk, int32_t reg, void* stream, bool virt)
         x.pgrp = reinterpret_cast<const ProlongGroup*>(pk->ws + pk->ws_pgrp);
         x.npgrp = (int64_t)pk->pgrp.size();
         x.npts = pk->p.nghost + 1;
-        e = launch_xlevel(pk->p.precision, x, as_stream(stream));
+        e = launch_xlevel(pk->p.precision, x, s);
+    }
+    // join even after a failed launch, so that a capture on s stays closed
+    if (fork) {
+        const hipError_t j = hipStreamWaitEvent(s, pk->join_ev, 0);
+        if (e == hipSuccess) e = j;
     }
     if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "ghost fill launch: %s", hipGetErrorString(e));
     return Z4C_OK;

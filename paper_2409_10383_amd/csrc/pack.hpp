@@ -65,6 +65,10 @@ struct z4c_pack {
     hipGraphExec_t gexec = nullptr;
     double graph_dt = 0.0;
     hipStream_t graph_stream = nullptr;
+    // multi-level packs: the same-level fill runs on a side stream beside the
+    // cross-level chain (fork and join through events on the caller's stream)
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     // optional kernel timing
     bool prof = false;
     struct EvPair { hipEvent_t a, b; int kind; };
