@@ -173,11 +173,18 @@ int z4c_block_offset(const struct z4c_pack *pack, int32_t b, int64_t *state_off,
  * least reg_bytes[r] each, 256-byte aligned; workspace of at least
  * workspace_bytes.  Uploads the block, neighbour and interpolation tables
  * into the workspace on `stream` (the call returns after the upload has been
- * enqueued; the workspace must not be reused while the pack is bound). */
+ * enqueued; the workspace must not be reused while the pack is bound).
+ * Packs with more than one refinement level also create, on the first bind
+ * and on the current device, one non-blocking stream of default priority and
+ * two events: each ghost fill forks its same-level copies onto that stream
+ * beside the cross-level work and joins back to the caller's stream before
+ * the call's next launch, so the caller sees stream-ordered results.
+ * Z4C_EDEVICE if the stream or events cannot be created. */
 int z4c_pack_bind(struct z4c_pack *pack, void *const regs[Z4C_NREG], void *workspace,
                   size_t workspace_bytes, void *stream);
 
-/* Free host metadata.  Device memory stays the caller's. */
+/* Free host metadata; waits for the side stream of a multi-level pack and
+ * destroys it.  Device memory stays the caller's. */
 void z4c_pack_destroy(struct z4c_pack *pack);
 
 /* Message of the last failed call on `pack` ("" if none). */
