@@ -54,6 +54,8 @@ def lib():
                                       C.c_double, C.c_double, C.c_int, C.c_double, dp, C.c_int,
                                       C.POINTER(C.c_int8)]
         L.or_psi4.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), dp, dp, dp]
+        L.or_rk4_update.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), C.c_int, C.c_double,
+                                    dp, dp, dp, dp, dp, C.POINTER(C.c_int8)]
         if hasattr(L, "or_block_features"):
             L.or_block_features.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), dp, dp]
         _lib = L
@@ -191,10 +193,46 @@ def rk4_stage(regs: Registers, params: dict, stage: int, dt: float) -> None:
         raise RuntimeError(f"oracle rk4 stage failed ({rc})")
 
 
-def rk4_steps(regs: Registers, params: dict, dt: float, nsteps: int) -> None:
+def rk4_steps(regs: Registers, params: dict, dt: float, nsteps: int, threads: int = 1) -> None:
+    """nsteps classic RK4 steps.  With threads > 1 each stage's RHS and
+    register update run on disjoint block sets in host threads (the same
+    per-zone arithmetic; the ghost fill stays serial)."""
     for _ in range(nsteps):
         for s in (1, 2, 3, 4):
-            rk4_stage(regs, params, s, dt)
+            if threads > 1:
+                rk4_stage_threaded(regs, params, s, dt, threads)
+            else:
+                rk4_stage(regs, params, s, dt)
+
+
+def rk4_stage_threaded(regs: Registers, params: dict, stage: int, dt: float, threads: int) -> None:
+    import concurrent.futures as cf
+    om = regs.om
+    src = {1: regs.U, 2: regs.S1, 3: regs.S2, 4: regs.S1}[stage]
+    fill_ghosts(om, src)
+    k = np.zeros(int(om.ioff[-1]))
+    prm = make_params(params)
+    nb = om.mesh.nb
+    # balance by zones: blocks dealt largest first to the least loaded thread
+    load = [0] * threads
+    masks = [np.zeros(nb, np.int8) for _ in range(threads)]
+    for b in sorted(range(nb), key=lambda b: -int(om.mesh.n[b])):
+        t = int(np.argmin(load))
+        masks[t][b] = 1
+        load[t] += int(om.mesh.n[b]) ** 3
+
+    def work(mask):
+        mp = mask.ctypes.data_as(C.POINTER(C.c_int8))
+        rc = lib().or_rhs_blocks(C.byref(om.c), C.byref(prm), _dp(src), _dp(k), mp)
+        if rc == 0:
+            rc = lib().or_rk4_update(C.byref(om.c), C.byref(prm), stage, dt, _dp(k), _dp(regs.U),
+                                     _dp(regs.S1), _dp(regs.S2), _dp(regs.A), mp)
+        return rc
+
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        rcs = list(ex.map(work, [m for m in masks if m.any()]))
+    if any(rcs):
+        raise RuntimeError(f"oracle rk4 stage failed ({rcs})")
 
 
 def constraints(om: OracleMesh, params: dict, u: np.ndarray, exclude=(), r_exc: float = 0.0,

@@ -63,25 +63,18 @@ static void enforce_zone(const or_params *p, double *v /* [ONF] */)
     if (v[O_ALPHA] < p->alpha_floor) v[O_ALPHA] = p->alpha_floor;
 }
 
-int or_rk4_stage(const or_mesh *m, const or_params *p, int stage, double dt, double *U,
-                 double *S1, double *S2, double *A)
+/* the register update of one stage from its right-hand side k (interior
+ * layout), for the blocks with only[b] != 0 (all when only is NULL) */
+int or_rk4_update(const or_mesh *m, const or_params *p, int stage, double dt, const double *k,
+                  double *U, double *S1, double *S2, double *A, const int8_t *only)
 {
     if (stage < 1 || stage > 4) return -1;
-    double *src = stage == 1 ? U : stage == 2 ? S1 : stage == 3 ? S2 : S1;
-    int rc = or_fill_ghosts(m, src);
-    if (rc) return rc;
-    /* interior RHS */
-    int64_t nint = 0;
-    for (int b = 0; b < m->nb; ++b) nint += (int64_t)ONF * m->n[b] * m->n[b] * m->n[b];
-    double *k = (double *)malloc(sizeof(double) * (nint > 0 ? nint : 1));
-    if (!k) return -2;
-    rc = or_rhs(m, p, src, k);
-    if (rc) { free(k); return rc; }
     int g = m->g;
     int64_t roff = 0;
     for (int b = 0; b < m->nb; ++b) {
         int n = m->n[b];
         int64_t E = n + 2 * g, off = or_block_offset(m, b), sf = E * E * E, sr = (int64_t)n * n * n;
+        if (only && !only[b]) { roff += (int64_t)ONF * sr; continue; }
         for (int kk = 0; kk < n; ++kk)
             for (int j = 0; j < n; ++j)
                 for (int i = 0; i < n; ++i) {
@@ -104,6 +97,23 @@ int or_rk4_stage(const or_mesh *m, const or_params *p, int stage, double dt, dou
                 }
         roff += (int64_t)ONF * sr;
     }
-    free(k);
     return 0;
+}
+
+int or_rk4_stage(const or_mesh *m, const or_params *p, int stage, double dt, double *U,
+                 double *S1, double *S2, double *A)
+{
+    if (stage < 1 || stage > 4) return -1;
+    double *src = stage == 1 ? U : stage == 2 ? S1 : stage == 3 ? S2 : S1;
+    int rc = or_fill_ghosts(m, src);
+    if (rc) return rc;
+    /* interior RHS */
+    int64_t nint = 0;
+    for (int b = 0; b < m->nb; ++b) nint += (int64_t)ONF * m->n[b] * m->n[b] * m->n[b];
+    double *k = (double *)malloc(sizeof(double) * (nint > 0 ? nint : 1));
+    if (!k) return -2;
+    rc = or_rhs(m, p, src, k);
+    if (!rc) rc = or_rk4_update(m, p, stage, dt, k, U, S1, S2, A, NULL);
+    free(k);
+    return rc;
 }

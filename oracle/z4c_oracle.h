@@ -76,6 +76,12 @@ int or_rhs_blocks(const or_mesh *m, const or_params *p, const double *u, double 
  * fills ghosts of the stage input itself. */
 int or_rk4_stage(const or_mesh *m, const or_params *p, int stage, double dt,
                  double *U, double *S1, double *S2, double *A);
+/* the register update of one stage (the writes above, with enforcement)
+ * from a precomputed RHS k (interior layout), only for blocks with
+ * only[b] != 0 (every block when only is NULL); ghosts are not touched, so
+ * disjoint block sets may run concurrently */
+int or_rk4_update(const or_mesh *m, const or_params *p, int stage, double dt, const double *k,
+                  double *U, double *S1, double *S2, double *A, const int8_t *only);
 
 /* constraints; out: interior layout with 8 components per zone
  * (H, Mx, My, Mz, Theta, Gx, Gy, Gz); norms[6] = H_L2, H_Linf, M_L2, M_Linf,

@@ -229,6 +229,17 @@ class Pack:
             per = 256 // esz
             self.slab.append((E ** 3 + per - 1) // per * per)
 
+    def rebind(self, stream=None):
+        """Move the pack to freshly allocated registers and workspace (their
+        contents copied over) through z4c_pack_bind."""
+        import torch
+        self.regs = [t.clone() for t in self.regs]
+        self.workspace = self.workspace.clone()
+        torch.cuda.synchronize()
+        ptrs = (C.c_void_p * NREG)(*[t.data_ptr() for t in self.regs])
+        self._check(lib().z4c_pack_bind(self.h, ptrs, C.c_void_p(self.workspace.data_ptr()),
+                                        self.workspace.numel(), _stream_ptr(stream)))
+
     # ------------------------------------------------------------ helpers
     def _check(self, rc):
         if rc:

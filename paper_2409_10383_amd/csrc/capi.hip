@@ -738,6 +738,11 @@ int z4c_pack_bind(z4c_pack* pk, void* const regs[Z4C_NREG], void* workspace, siz
             return fail(pk, Z4C_EDEVICE, "side stream: %s", hipGetErrorString(e));
         }
     }
+    // a step graph captured against the previous registers / workspace holds
+    // their addresses in its kernel arguments: drop it, the next graph step
+    // captures again
+    if (pk->gexec) { hipGraphExecDestroy(pk->gexec); pk->gexec = nullptr; }
+    if (pk->graph) { hipGraphDestroy(pk->graph); pk->graph = nullptr; }
     for (int r = 0; r < Z4C_NREG; ++r) pk->reg[r] = regs[r];
     pk->ws = ws;
     pk->bound = true;

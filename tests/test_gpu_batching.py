@@ -77,3 +77,31 @@ def test_autotune_selects_fastest_valid():
     r1 = pk.rhs().cpu().numpy()
     pk.set_variant(0, False)
     assert np.array_equal(pk.rhs().cpu().numpy(), r1)
+
+
+def test_graph_step_after_rebind_uses_new_registers():
+    """Re-binding a pack to new registers drops its captured step graph: a
+    graph step after z4c_pack_bind reads and writes the new registers, and
+    equals an eager step bitwise (the old registers stay untouched)."""
+    mesh, p, data = mixed_pack(6)
+    dt = 0.25 * mesh.dx_min()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        eager = z().Pack(mesh, p)
+        eager.upload(z().REG_U, data)
+        graph = z().Pack(mesh, dict(p, graph=1))
+        graph.upload(z().REG_U, data)
+        torch.cuda.synchronize()
+        graph.rk4_step(dt, 1, stream=s)
+        eager.rk4_step(dt, 1, stream=s)
+        s.synchronize()
+        old = graph.regs
+        old_u = old[z().REG_U].clone()
+        graph.rebind(stream=s)
+        graph.rk4_step(dt, 1, stream=s)
+        eager.rk4_step(dt, 1, stream=s)
+        s.synchronize()
+        a = graph.state_view(z().REG_U).cpu().numpy()
+        b = eager.state_view(z().REG_U).cpu().numpy()
+        assert np.array_equal(a, b, equal_nan=True)
+        assert torch.equal(old[z().REG_U], old_u)
