@@ -43,6 +43,7 @@ def lib():
         dp = C.POINTER(C.c_double)
         L.or_fd_weights.argtypes = [C.c_int, C.c_int, dp, dp]
         L.or_fill_ghosts.argtypes = [C.POINTER(_Mesh), dp]
+        L.or_fill_ghosts_from.argtypes = [C.POINTER(_Mesh), dp, dp, C.POINTER(C.c_int8)]
         L.or_rhs.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), dp, dp]
         L.or_rhs_blocks.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), dp, dp,
                                     C.POINTER(C.c_int8)]
@@ -152,26 +153,70 @@ def fd_weights(deriv: int, pts) -> np.ndarray:
     return w
 
 
-def fill_ghosts(om: OracleMesh, u: np.ndarray) -> None:
-    rc = lib().or_fill_ghosts(C.byref(om.c), _dp(u))
-    if rc:
-        raise RuntimeError(f"oracle ghost fill failed ({rc})")
+def fill_ghosts(om: OracleMesh, u: np.ndarray, threads: int = 1) -> None:
+    """Ghost fill of every block of u; with threads > 1 disjoint block sets
+    are filled in host threads from one copy of u (same values)."""
+    if threads <= 1:
+        rc = lib().or_fill_ghosts(C.byref(om.c), _dp(u))
+        if rc:
+            raise RuntimeError(f"oracle ghost fill failed ({rc})")
+        return
+    import concurrent.futures as cf
+    src = u.copy()
+    # ghost-heavy blocks are the small ones: balance by ghost count
+    nb, g = om.mesh.nb, om.mesh.g
+    load = [0] * threads
+    masks = [np.zeros(nb, np.int8) for _ in range(threads)]
+    ghosts = [(int(n) + 2 * g) ** 3 - int(n) ** 3 for n in om.mesh.n]
+    for b in sorted(range(nb), key=lambda b: -ghosts[b]):
+        t = int(np.argmin(load))
+        masks[t][b] = 1
+        load[t] += ghosts[b]
+
+    def work(mask):
+        return lib().or_fill_ghosts_from(C.byref(om.c), _dp(src), _dp(u),
+                                         mask.ctypes.data_as(C.POINTER(C.c_int8)))
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        rcs = list(ex.map(work, [m for m in masks if m.any()]))
+    if any(rcs):
+        raise RuntimeError(f"oracle ghost fill failed ({rcs})")
 
 
-def rhs(om: OracleMesh, params: dict, u: np.ndarray, fill: bool = True, blocks=None):
+def _thread_masks(om: OracleMesh, blocks, threads: int):
+    """Block masks for `threads` host threads, balanced by zones."""
+    nb = om.mesh.nb
+    sel = range(nb) if blocks is None else sorted(set(int(b) for b in blocks))
+    load = [0] * threads
+    masks = [np.zeros(nb, np.int8) for _ in range(threads)]
+    for b in sorted(sel, key=lambda b: -int(om.mesh.n[b])):
+        t = int(np.argmin(load))
+        masks[t][b] = 1
+        load[t] += int(om.mesh.n[b]) ** 3
+    return [m for m in masks if m.any()]
+
+
+def rhs(om: OracleMesh, params: dict, u: np.ndarray, fill: bool = True, blocks=None,
+        threads: int = 1):
     """Per-block RHS interiors (22, n, n, n); fills ghosts of u first.  With
-    `blocks`, only those blocks are computed (the others stay zero)."""
+    `blocks`, only those blocks are computed (the others stay zero); with
+    threads > 1 disjoint block sets run in host threads (same arithmetic)."""
+    import concurrent.futures as cf
     if fill:
-        fill_ghosts(om, u)
+        fill_ghosts(om, u, threads)
     r = np.zeros(int(om.ioff[-1]))
-    only = None
-    if blocks is not None:
-        mask = np.zeros(om.mesh.nb, np.int8)
-        mask[list(blocks)] = 1
-        only = mask.ctypes.data_as(C.POINTER(C.c_int8))
-    rc = lib().or_rhs_blocks(C.byref(om.c), C.byref(make_params(params)), _dp(u), _dp(r), only)
-    if rc:
-        raise RuntimeError(f"oracle rhs failed ({rc})")
+    prm = make_params(params)
+    if threads <= 1 and blocks is None:
+        masks = [None]
+    else:
+        masks = _thread_masks(om, blocks, max(1, threads))
+
+    def work(mask):
+        only = None if mask is None else mask.ctypes.data_as(C.POINTER(C.c_int8))
+        return lib().or_rhs_blocks(C.byref(om.c), C.byref(prm), _dp(u), _dp(r), only)
+    with cf.ThreadPoolExecutor(max_workers=max(1, len(masks))) as ex:
+        rcs = list(ex.map(work, masks))
+    if any(rcs):
+        raise RuntimeError(f"oracle rhs failed ({rcs})")
     return om.split_interior(r)
 
 
@@ -209,17 +254,10 @@ def rk4_stage_threaded(regs: Registers, params: dict, stage: int, dt: float, thr
     import concurrent.futures as cf
     om = regs.om
     src = {1: regs.U, 2: regs.S1, 3: regs.S2, 4: regs.S1}[stage]
-    fill_ghosts(om, src)
+    fill_ghosts(om, src, threads)
     k = np.zeros(int(om.ioff[-1]))
     prm = make_params(params)
-    nb = om.mesh.nb
-    # balance by zones: blocks dealt largest first to the least loaded thread
-    load = [0] * threads
-    masks = [np.zeros(nb, np.int8) for _ in range(threads)]
-    for b in sorted(range(nb), key=lambda b: -int(om.mesh.n[b])):
-        t = int(np.argmin(load))
-        masks[t][b] = 1
-        load[t] += int(om.mesh.n[b]) ** 3
+    masks = _thread_masks(om, None, threads)
 
     def work(mask):
         mp = mask.ctypes.data_as(C.POINTER(C.c_int8))
@@ -230,7 +268,7 @@ def rk4_stage_threaded(regs: Registers, params: dict, stage: int, dt: float, thr
         return rc
 
     with cf.ThreadPoolExecutor(max_workers=threads) as ex:
-        rcs = list(ex.map(work, [m for m in masks if m.any()]))
+        rcs = list(ex.map(work, masks))
     if any(rcs):
         raise RuntimeError(f"oracle rk4 stage failed ({rcs})")
 

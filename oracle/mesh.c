@@ -296,22 +296,16 @@ static int composite_values(const or_mesh *m, const lookup_t *L, const double *u
     return -1;
 }
 
-int or_fill_ghosts(const or_mesh *m, double *u)
+int or_fill_ghosts_from(const or_mesh *m, const double *src, double *u, const int8_t *only)
 {
     if (m->bc == 2) return 0;
     lookup_t L;
     if (lookup_build(m, &L)) { lookup_free(&L); return -1; }
     int rc = 0;
     int g = m->g;
-    /* Values are computed from active zones only, so the result does not
-     * depend on the order blocks are visited.  Compute from a copy so that
-     * no ghost is read while being written. */
-    int64_t tot = or_total_size(m);
-    double *src = (double *)malloc(sizeof(double) * tot);
-    if (!src) { lookup_free(&L); return -2; }
-    memcpy(src, u, sizeof(double) * tot);
     memo_t M = {0, 0, NULL, NULL};
     for (int b = 0; b < m->nb && !rc; ++b) {
+        if (only && !only[b]) continue;
         int n = m->n[b], l = m->level[b];
         int64_t E = n + 2 * g, off = L.off[b];
         for (int k = 0; k < E && !rc; ++k)
@@ -328,7 +322,21 @@ int or_fill_ghosts(const or_mesh *m, double *u)
     }
     free(M.key);
     free(M.val);
-    free(src);
     lookup_free(&L);
+    return rc;
+}
+
+int or_fill_ghosts(const or_mesh *m, double *u)
+{
+    if (m->bc == 2) return 0;
+    /* Values are computed from active zones only, so the result does not
+     * depend on the order blocks are visited.  Compute from a copy so that
+     * no ghost is read while being written. */
+    int64_t tot = or_total_size(m);
+    double *src = (double *)malloc(sizeof(double) * (tot > 0 ? tot : 1));
+    if (!src) return -2;
+    memcpy(src, u, sizeof(double) * tot);
+    int rc = or_fill_ghosts_from(m, src, u, NULL);
+    free(src);
     return rc;
 }

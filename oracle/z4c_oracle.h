@@ -65,6 +65,10 @@ int64_t or_total_size(const or_mesh *m);
 
 /* ghost fill of every block of a register (all fields) */
 int or_fill_ghosts(const or_mesh *m, double *u);
+/* the ghosts of the blocks with only[b] != 0 (all when NULL) written into u,
+ * every value computed from the active zones of src (a copy of u): disjoint
+ * block sets may run concurrently */
+int or_fill_ghosts_from(const or_mesh *m, const double *src, double *u, const int8_t *only);
 
 /* RHS of all interior zones; u must have ghosts filled. rhs: interior layout */
 int or_rhs(const or_mesh *m, const or_params *p, const double *u, double *rhs);

@@ -630,6 +630,7 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
     pk->ws_feat = o;   o = align256(o + sizeof(double) * 16 * nblocks);
     pk->ws_x = o;      o = align256(o + sizeof(float) * 16 * nblocks);
     pk->ws_y = o;      o = align256(o + sizeof(float) * nblocks);
+    pk->ws_lflag = o;  o = align256(o + 2 * (size_t)nblocks);
     pk->ws_xfer = o;   o = align256(o + sizeof(XferItem) * pk->xfer.size());
     pk->ws_prol = o;   o = align256(o + sizeof(ProlongItem) * pk->prol.size());
     pk->ws_pgrp = o;   o = align256(o + sizeof(ProlongGroup) * pk->pgrp.size());
@@ -1300,42 +1301,32 @@ int z4c_refine_flags_learned(z4c_pack* pk, int32_t reg, const z4c_mlp_model* md,
     if (!pk) return Z4C_EINVAL;
     if (!md || !md->params || !md->stats || !md->range || !flags_out) return fail(pk, Z4C_EINVAL, "null argument");
     const int nb = (int)pk->blk.size();
-    std::vector<double> feat(16 * nb);
     int rc = z4c_features(pk, reg, nullptr, nullptr, stream);
     if (rc) return rc;
     hipStream_t s = as_stream(stream);
     double* fdev = reinterpret_cast<double*>(pk->ws + pk->ws_feat);
     float* X = reinterpret_cast<float*>(pk->ws + pk->ws_x);
     float* Y = reinterpret_cast<float*>(pk->ws + pk->ws_y);
+    int8_t* fl = reinterpret_cast<int8_t*>(pk->ws + pk->ws_lflag);
+    LearnedRule r;
+    std::memset(&r, 0, sizeof(r));
+    for (int k = 0; k < 16; ++k) { r.lo[k] = md->range[k]; r.hi[k] = md->range[16 + k]; }
+    r.tau_ref = md->tau_ref;
+    r.tau_deref = md->tau_deref;
+    r.chi_thr = md->chi_thr;
+    r.dchi_thr = md->dchi_thr;
+    r.level_max = md->level_max;
+    std::vector<int8_t> host(2 * (size_t)nb);
     hipError_t e = launch_normalize(fdev, nb, static_cast<const double*>(md->stats), X, s);
     if (e == hipSuccess) e = launch_mlp_forward(static_cast<const float*>(md->params), X, nb, Y, nullptr, s);
-    std::vector<float> yh(nb);
-    if (e == hipSuccess) e = hipMemcpyAsync(yh.data(), Y, sizeof(float) * nb, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(feat.data(), fdev, sizeof(double) * 16 * nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = launch_learned_flags(fdev, Y, reinterpret_cast<const BlockDev*>(pk->ws + pk->ws_blocks), nb, r, fl,
+                                 fl + nb, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host.data(), fl, 2 * (size_t)nb, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "learned flags: %s", hipGetErrorString(e));
-    for (int b = 0; b < nb; ++b) {
-        const int lev = pk->blk[b].level;
-        bool ood = !std::isfinite((double)yh[b]);
-        for (int k = 0; k < 16; ++k) {
-            const double r = feat[16 * b + k];
-            const double phi = k < 15 ? std::log10(std::fabs(r) + 1e-12) : r;
-            const double lo = md->range[k], hi = md->range[16 + k], pad = 0.1 * (hi - lo);
-            if (!std::isfinite(phi) || phi < lo - pad || phi > hi + pad) ood = true;
-        }
-        int f;
-        if (ood) {
-            const double gmax = feat[16 * b + 0];
-            f = gmax > md->dchi_thr ? 1 : (gmax < 0.5 * md->dchi_thr ? -1 : 0);
-        } else {
-            f = yh[b] > md->tau_ref ? 1 : (yh[b] < md->tau_deref ? -1 : 0);
-        }
-        if (feat[16 * b + 7] < md->chi_thr) f = 1;
-        if (f > 0 && lev >= md->level_max) f = 0;
-        if (f < 0 && lev == 0) f = 0;
-        flags_out[b] = (int8_t)f;
-        if (fallback_out) fallback_out[b] = ood ? 1 : 0;
-    }
+    std::memcpy(flags_out, host.data(), (size_t)nb);
+    if (fallback_out) std::memcpy(fallback_out, host.data() + nb, (size_t)nb);
     return Z4C_OK;
 }
 

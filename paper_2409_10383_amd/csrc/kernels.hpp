@@ -144,6 +144,15 @@ hipError_t launch_mlp_backward(const float* P, const float* X, const float* Y, c
 hipError_t launch_mlp_adam(float* P, const float* G, float* M, float* V, int step, float lr, float b1,
                            float b2, float eps, hipStream_t s);
 hipError_t launch_normalize(const double* raw, int B, const double* stats, float* X, hipStream_t s);
+// the rules of the learned refinement flags (training range of phi per
+// feature, thresholds, level limit)
+struct LearnedRule {
+    double lo[16], hi[16];
+    double tau_ref, tau_deref, chi_thr, dchi_thr;
+    int32_t level_max, pad;
+};
+hipError_t launch_learned_flags(const double* feat, const float* Y, const BlockDev* blocks, int nb,
+                                const LearnedRule& r, int8_t* flags, int8_t* fallback, hipStream_t s);
 hipError_t launch_feat_stats(const double* raw, int B, double* stats, hipStream_t s);
 
 hipError_t launch_stage(int N, int prec, int variant, const StageArgs& a, int grid, hipStream_t s);

@@ -385,6 +385,43 @@ hipError_t launch_mlp_adam(float* P, const float* G, float* M, float* V, int ste
     return hipGetLastError();
 }
 
+// Learned refinement flags of one block per thread: +1 if the prediction
+// exceeds tau_ref, -1 below tau_deref, else 0; a block whose prediction or
+// phi(features) is non-finite or outside the training range widened by 10 %
+// takes the dchi-max flag instead (max|d chi| > thr: +1, < thr/2: -1);
+// min chi < chi_thr forces +1; no +1 at level_max, no -1 at level 0.
+__global__ void k_learned_flags(const double* feat, const float* Y, const BlockDev* blocks, int nb,
+                                const LearnedRule r, int8_t* flags, int8_t* fallback)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const double* f = feat + (int64_t)b * NFEAT;
+    const double y = (double)Y[b];
+    bool ood = !isfinite(y);
+    for (int k = 0; k < NFEAT; ++k) {
+        const double phi = k < 15 ? log10(fabs(f[k]) + 1e-12) : f[k];
+        const double lo = r.lo[k], hi = r.hi[k], pad = 0.1 * (hi - lo);
+        if (!isfinite(phi) || phi < lo - pad || phi > hi + pad) ood = true;
+    }
+    int fl;
+    if (ood) fl = f[0] > r.dchi_thr ? 1 : (f[0] < 0.5 * r.dchi_thr ? -1 : 0);
+    else fl = y > r.tau_ref ? 1 : (y < r.tau_deref ? -1 : 0);
+    if (f[7] < r.chi_thr) fl = 1;
+    const int lev = blocks[b].level;
+    if (fl > 0 && lev >= r.level_max) fl = 0;
+    if (fl < 0 && lev == 0) fl = 0;
+    flags[b] = (int8_t)fl;
+    fallback[b] = ood ? 1 : 0;
+}
+
+hipError_t launch_learned_flags(const double* feat, const float* Y, const BlockDev* blocks, int nb,
+                                const LearnedRule& r, int8_t* flags, int8_t* fallback, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_learned_flags, dim3((nb + 255) / 256), dim3(256), 0, s, feat, Y, blocks, nb, r,
+                       flags, fallback);
+    return hipGetLastError();
+}
+
 hipError_t launch_normalize(const double* raw, int B, const double* stats, float* X, hipStream_t s)
 {
     hipLaunchKernelGGL(k_normalize, dim3((B * NFEAT + 255) / 256), dim3(256), 0, s, raw, B, stats, X);

@@ -43,7 +43,7 @@ struct z4c_pack {
     size_t ws_track = 0;
     size_t ws_flag = 0;       // finite-value check flag (int32)
     std::vector<double> track_host;
-    size_t ws_first = 0, ws_feat = 0, ws_x = 0, ws_y = 0;
+    size_t ws_first = 0, ws_feat = 0, ws_x = 0, ws_y = 0, ws_lflag = 0;
     std::vector<int32_t> first_work;
     int maxghost = 0;
     int64_t zones = 0;

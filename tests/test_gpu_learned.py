@@ -144,3 +144,98 @@ def test_training_beats_dchi_max_at_equal_budget():
         gains.append((len(truth & learned) - len(truth & dchi)) / K)
     assert np.mean(gains) >= 0.0, gains
     print("precision@K gain over dchi-max:", np.mean(gains), gains)
+
+
+def _phi(raw):
+    phi = np.log10(np.abs(raw) + 1e-12)
+    phi[:, 15] = raw[:, 15]
+    return phi
+
+
+def _gap_point(vals, q, margin):
+    """A threshold near quantile q of vals that lies at least `margin` from
+    every value (midpoint of the widest nearby gap)."""
+    v = np.sort(np.unique(vals))
+    mids = 0.5 * (v[1:] + v[:-1])
+    gaps = v[1:] - v[:-1]
+    ok = np.where(gaps > 2 * margin)[0]
+    assert ok.size, "no usable gap"
+    target = np.quantile(v, q)
+    return float(mids[ok[np.argmin(np.abs(mids[ok] - target))]])
+
+
+def learned_rules(raw, y, levels, rng_, tau_ref, tau_deref, chi_thr, dchi_thr, level_max):
+    """The rules of z4c_refine_flags_learned written out (header of
+    include/z4c.h): network thresholds, out-of-distribution fallback to
+    dchi-max with its derefine hysteresis, chi-min safety, level limits.
+    Returns (flags, fallback, flags before the level limits)."""
+    phi = _phi(raw)
+    lo, hi = rng_[:16], rng_[16:]
+    pad = 0.1 * (hi - lo)
+    ood = (~np.isfinite(y)) | np.any(~np.isfinite(phi) | (phi < lo - pad) | (phi > hi + pad), axis=1)
+    net = np.where(y > tau_ref, 1, np.where(y < tau_deref, -1, 0))
+    g = raw[:, 0]
+    dchi = np.where(g > dchi_thr, 1, np.where(g < 0.5 * dchi_thr, -1, 0))
+    f = np.where(ood, dchi, net)
+    f = np.where(raw[:, 7] < chi_thr, 1, f)
+    pre = f.copy()
+    f = np.where((f > 0) & (levels >= level_max), 0, f)
+    f = np.where((f < 0) & (levels == 0), 0, f)
+    return f.astype(np.int8), ood.astype(np.int8), pre
+
+
+def test_learned_flags_rules_against_reference():
+    """z4c_refine_flags_learned against the rules written out in numpy on the
+    oracle's features and the bfloat16-emulating oracle network: a two-level
+    two-puncture pack whose network saw only level-0 statistics for log2 dx,
+    so every level-1 block is out of distribution and falls back to dchi-max;
+    blocks next to the punctures have min chi < chi_thr (forced +1); level
+    limits at level 0 and at level_max.  Thresholds sit in gaps of the
+    predictions and features, so both sides take every decision the same
+    way."""
+    base = zi.uniform_mesh((4, 4, 4), 16, 4, (-8.0,) * 3, (8.0,) * 3, zi.BC_OUTFLOW)
+    mesh = zi.refine_blocks(base, zi.blocks_in_box(base, (-4.0,) * 3, (4.0,) * 3))
+    data = zi.brill_lindquist(mesh, [(0.5, (2.0, 0.0, 0.0)), (0.5, (-2.0, 0.0, 0.0))])
+    data = zi.add_perturbation(mesh, data, seed=13, amp=1e-6)
+    p = zi.params_default(6)
+    om = oracle.OracleMesh(mesh)
+    raw = oracle.block_features(om, p, om.scatter(data))
+    levels = np.asarray(mesh.level)
+    phi = _phi(raw)
+    mean, std = phi.mean(0), np.maximum(phi.std(0), 1e-3)
+    rng_ = np.concatenate([phi.min(0), phi.max(0)])
+    rng_[15] = rng_[16 + 15] = np.log2(mesh.dx0)      # network trained on level 0 only
+    params = omlp.init(3)
+    X = ((phi - mean) / std).astype(np.float32)
+    y, _ = omlp.forward(params, X.astype(np.float64))
+    ood_ref = levels > 0
+    tau_deref = _gap_point(y[~ood_ref], 0.3, 2e-3)
+    tau_ref = _gap_point(y[~ood_ref], 0.7, 2e-3)
+    chi_thr = 0.3
+    # dchi threshold t: compared with g and with 2g (g < t/2), so it sits in a
+    # gap of both sets, chosen to give the fallback all three outcomes
+    g = raw[ood_ref, 0]
+    u = np.unique(np.concatenate([g, 2 * g]))
+    mids = 0.5 * (u[1:] + u[:-1])
+    cand = mids[(u[1:] - u[:-1]) > 1e-5 * mids]
+    dchi_thr = float(max(cand, key=lambda t: len(set(np.where(g > t, 1, np.where(g < 0.5 * t, -1, 0))))))
+    stats = np.concatenate([mean, std, phi.min(0), phi.max(0)])
+
+    net = z().Mlp(params)
+    net.stats.copy_(torch.tensor(stats, dtype=torch.float64))
+    pk = z().Pack(mesh, p)
+    pk.upload(z().REG_U, data)
+    for level_max in (1, 2):
+        want, fb_want, pre = learned_rules(raw, y, levels, rng_, tau_ref, tau_deref, chi_thr, dchi_thr,
+                                           level_max)
+        flags, fb = z().refine_flags_learned(pk, net, rng_, tau_ref, tau_deref, chi_thr=chi_thr,
+                                             dchi_thr=dchi_thr, level_max=level_max)
+        assert np.array_equal(fb, fb_want), np.where(fb != fb_want)
+        assert np.array_equal(flags, want), np.where(flags != want)
+        # every rule was exercised
+        assert fb_want.any() and (~fb_want.astype(bool)).any()
+        assert (raw[:, 7] < chi_thr).any()
+        assert ((pre < 0) & (levels == 0)).any()
+        if level_max == 1:
+            assert ((pre > 0) & (levels >= 1)).any()
+        assert set(np.unique(want[fb_want == 0])) >= {0, 1}

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import z4c_inputs as zi
-from _parity import assert_parity
+from _parity import ORACLE_THREADS, assert_parity, oracle_steps, rounding_floor
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -67,16 +67,19 @@ def test_cross_level_rhs_and_step(order):
     assert_parity(rg, ro, what="rhs")
     dt = 0.25 * mesh.dx_min()
     pk.rk4_step(dt, 1)
-    regs = oracle.Registers(om, data)
-    oracle.rk4_steps(regs, p, dt, 1)
+    want, floor = oracle_steps(mesh, p, data, dt, 1)
     torch.cuda.synchronize()
-    assert_parity(pk.download(z().REG_U), om.interiors(regs.U), what="step", mode="state")
+    assert_parity(pk.download(z().REG_U), want, what="step", floor=floor)
 
 
-def test_bbh512mixed_full_size():
+def test_bbh512mixed_ghosts_and_rhs_all_blocks():
     """The 512-block, 4-level, 16^3/32^3 two-puncture pack at full size
-    (8th order, 5 ghosts): every ghost cell against the oracle, and the RHS
-    on a sample of blocks at every level and size."""
+    (8th order, 5 ghosts): every ghost cell, and the RHS of every zone of all
+    512 blocks, against the oracle.  The RHS bar is per field; near the
+    punctures d_t Theta is a small residual of large cancelling terms (it is
+    proportional to H ~ 0 on this constraint-satisfying data), so each field
+    gets the oracle's own rounding floor (its response to one-ulp changes of
+    the input)."""
     mesh, p, data, dt, _ = zi.workload("bbh512mixed")
     pk = z().Pack(mesh, p)
     pk.upload(z().REG_U, data)
@@ -85,29 +88,35 @@ def test_bbh512mixed_full_size():
     got = pk.download(z().REG_U, ghosted=True)
     om = oracle.OracleMesh(mesh)
     u = om.scatter(data)
-    oracle.fill_ghosts(om, u)
+    oracle.fill_ghosts(om, u, ORACLE_THREADS)
     want = [om.block_view(u, b) for b in range(mesh.nb)]
     assert_parity(got, want, what="ghosts bbh512mixed")
-    rng = np.random.default_rng(0)
-    sample = []
-    for lev in range(4):
-        for n in (16, 32):
-            cand = np.where((mesh.level == lev) & (mesh.n == n))[0]
-            if cand.size:
-                sample += list(rng.choice(cand, size=min(3, cand.size), replace=False))
-    # include the blocks holding the punctures, where the RHS is largest
-    for xp in (5.0, -5.0):
-        for b in range(mesh.nb):
-            hb = mesh.dx(b)
-            x0 = [mesh.lo[a] + mesh.ilo[b, a] * hb for a in range(3)]
-            if all(x0[a] <= (xp, 0.0, 0.0)[a] <= x0[a] + mesh.n[b] * hb for a in range(3)):
-                sample.append(b)
-    sample = sorted(set(int(b) for b in sample))
-    ro = oracle.rhs(om, p, u, fill=False, blocks=sample)
-    S = max(np.abs(data[b][[0, 1, 4, 6, 18]]).max() for b in sample)
-    hmin = mesh.dx_min()
-    assert_parity([rg[b] for b in sample], [ro[b] for b in sample], what="rhs bbh512mixed sample",
-                  mode="rounding", S=S, order=8, h=hmin)
+    del got, want
+
+    def run(d):
+        return oracle.rhs(om, p, om.scatter(d), threads=ORACLE_THREADS)
+    ro, floor = rounding_floor(run, data)
+    assert_parity(rg, ro, what="rhs bbh512mixed, all blocks", floor=floor)
+
+
+def test_bbh512mixed_step_graph_autotuned():
+    """One RK4 step of the full 512-block pack exactly as the benchmark runs
+    it: hipGraph-captured step (ghost fills on the pack's side stream inside
+    the capture), autotuned tile and launch mode, one fused launch per stage;
+    every zone of every field against one oracle step of the whole mesh."""
+    mesh, p, data, dt, _ = zi.workload("bbh512mixed")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        pk = z().Pack(mesh, dict(p, graph=1))
+        pk.upload(z().REG_U, data)
+        chosen, _ = pk.autotune(reps=1, stream=s)
+        pk.rk4_step(dt, 1, stream=s)
+        s.synchronize()
+        got = pk.download(z().REG_U)
+    del pk
+    torch.cuda.empty_cache()
+    want, floor = oracle_steps(mesh, p, data, dt, 1)
+    assert_parity(got, want, what=f"graph step bbh512mixed (variant {chosen})", floor=floor)
 
 
 def test_fill_is_ordered_on_the_callers_stream():

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import z4c_inputs as zi
-from _parity import assert_parity
+from _parity import assert_parity, field_errors, oracle_steps, ulp_perturbed, K_ROUND
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -95,21 +95,30 @@ def test_rhs_parity_term_masks(terms):
 
 
 def test_rk4_stages_parity_periodic16():
+    """Each stage's output register and the FP64 accumulator, stage by stage
+    (evolved-state bar: the oracle runs the same stages from inputs moved by
+    one ulp beside it for the per-field rounding floor)."""
     mesh, p, data, dt, _ = zi.workload("periodic16")
     pk = z().Pack(mesh, p)
     pk.upload(z().REG_U, data)
     om = oracle.OracleMesh(mesh)
     regs = oracle.Registers(om, data)
+    alt = oracle.Registers(om, ulp_perturbed(data))
     for stage in (1, 2, 3, 4):
         pk.rk4_stage(stage, dt)
         oracle.rk4_stage(regs, p, stage, dt)
+        oracle.rk4_stage(alt, p, stage, dt)
         torch.cuda.synchronize()
         reg = {1: 1, 2: 2, 3: 1, 4: 0}[stage]
-        ora = {0: regs.U, 1: regs.S1, 2: regs.S2}[reg]
-        assert_parity(pk.download(reg), om.interiors(ora), what=f"stage {stage}", mode="state")
+        name = {0: "U", 1: "S1", 2: "S2"}[reg]
+        ora, oalt = om.interiors(getattr(regs, name)), om.interiors(getattr(alt, name))
+        floor = K_ROUND * field_errors(oalt, ora)[1]
+        assert_parity(pk.download(reg), ora, what=f"stage {stage}", floor=floor)
         if stage < 4:
             acc = pk.split_interior(pk.acc_view())
-            assert_parity(acc, om.interiors(regs.A), what=f"accumulator stage {stage}", mode="state")
+            oa, oaa = om.interiors(regs.A), om.interiors(alt.A)
+            assert_parity(acc, oa, what=f"accumulator stage {stage}",
+                          floor=K_ROUND * field_errors(oaa, oa)[1])
 
 
 def test_rk4_steps_parity_bl():
@@ -121,11 +130,9 @@ def test_rk4_steps_parity_bl():
     pk = z().Pack(mesh, p)
     pk.upload(z().REG_U, data)
     pk.rk4_step(dt, 2)
-    om = oracle.OracleMesh(mesh)
-    regs = oracle.Registers(om, data)
-    oracle.rk4_steps(regs, p, dt, 2)
+    want, floor = oracle_steps(mesh, p, data, dt, 2)
     torch.cuda.synchronize()
-    assert_parity(pk.download(0), om.interiors(regs.U), what="2 steps BL", mode="state")
+    assert_parity(pk.download(0), want, what="2 steps BL", floor=floor)
 
 
 def test_constraints_parity():
@@ -174,10 +181,8 @@ def test_bl64x32_full_size_step_in_bench_launch_configuration():
     pk.rk4_step(dt, 1)
     torch.cuda.synchronize()
     got = pk.download(z().REG_U)
-    om = oracle.OracleMesh(mesh)
-    regs = oracle.Registers(om, data)
-    oracle.rk4_steps(regs, p, dt, 1)
-    assert_parity(got, om.interiors(regs.U), what=f"step bl64x32 (variant {chosen})", mode="state")
+    want, floor = oracle_steps(mesh, p, data, dt, 1)
+    assert_parity(got, want, what=f"step bl64x32 (variant {chosen})", floor=floor)
 
 
 @pytest.mark.parametrize("n", [64, 128])
@@ -197,11 +202,8 @@ def test_large_block_parity(n):
         chosen, _ = pk.autotune(reps=1)
         pk.rk4_step(dt, 1)
         torch.cuda.synchronize()
-        om = oracle.OracleMesh(mesh)
-        regs = oracle.Registers(om, data)
-        oracle.rk4_steps(regs, p, dt, 1)
-        assert_parity(pk.download(z().REG_U), om.interiors(regs.U), what=f"step 64^3 (variant {chosen})",
-                      mode="state")
+        want, floor = oracle_steps(mesh, p, data, dt, 1)
+        assert_parity(pk.download(z().REG_U), want, what=f"step 64^3 (variant {chosen})", floor=floor)
 
 
 # tile counts that are not a multiple of 8 (the XCD-interleaved slot map has
@@ -228,11 +230,9 @@ def test_ragged_tile_count_parity(shape, persistent):
     dt = 0.25 * mesh.dx0
     pk.upload(z().REG_U, data)
     pk.rk4_step(dt, 1)
-    om = oracle.OracleMesh(mesh)
-    regs = oracle.Registers(om, data)
-    oracle.rk4_steps(regs, p, dt, 1)
+    want, floor = oracle_steps(mesh, p, data, dt, 1)
     torch.cuda.synchronize()
-    assert_parity(pk.download(0), om.interiors(regs.U), what=f"step {shape}", mode="state")
+    assert_parity(pk.download(0), want, what=f"step {shape}", floor=floor)
 
 
 @pytest.mark.parametrize("graph", [False, True])
@@ -258,3 +258,36 @@ def test_check_finite_flag(graph):
         quiet.rk4_step(dt, 1, stream=s)
         torch.cuda.synchronize()
         assert not np.isfinite(quiet.download(z().REG_U)[3]).all()
+
+
+def floored_bl():
+    """Brill-Lindquist M = 1 on [-2, 2]^3 at dx = 1/8 with chi_floor = 1e-2
+    and alpha_floor = 5e-2: next to the puncture chi = psi^-4 ~ 1e-3 and
+    alpha = psi^-2 ~ 3e-2, so both floors act at every stage write and chi is
+    floored wherever it divides."""
+    mesh = zi.uniform_mesh((2, 2, 2), 16, 4, (-2.0,) * 3, (2.0,) * 3, zi.BC_OUTFLOW)
+    data = zi.brill_lindquist(mesh, [(1.0, (0.0, 0.0, 0.0))])
+    p = dict(zi.params_default(6), chi_floor=1e-2, alpha_floor=5e-2)
+    return mesh, p, data, 0.25 * mesh.dx0
+
+
+def test_floors_active_step_parity_fp64():
+    """R8 floors in action (moving-puncture data, Sec. 2): two RK4 steps with
+    both floors active against the oracle; the floored cells are the same and
+    hold the floor values exactly."""
+    mesh, p, data, dt = floored_bl()
+    assert min(d[0].min() for d in data) < p["chi_floor"]
+    assert min(d[18].min() for d in data) < p["alpha_floor"]
+    pk = z().Pack(mesh, p)
+    pk.upload(z().REG_U, data)
+    pk.rk4_step(dt, 2)
+    torch.cuda.synchronize()
+    got = pk.download(z().REG_U)
+    want, floor = oracle_steps(mesh, p, data, dt, 2)
+    nchi = sum(int((w[0] == p["chi_floor"]).sum()) for w in want)
+    nal = sum(int((w[18] == p["alpha_floor"]).sum()) for w in want)
+    assert nchi > 0 and nal > 0, (nchi, nal)
+    for g_, w_ in zip(got, want):
+        assert np.array_equal(g_[0] == p["chi_floor"], w_[0] == p["chi_floor"])
+        assert np.array_equal(g_[18] == p["alpha_floor"], w_[18] == p["alpha_floor"])
+    assert_parity(got, want, what="floored step", floor=floor)

@@ -168,3 +168,35 @@ def test_fp32_storage_constraints_and_interpolation_in_double():
     got = pk.interp_state(z().REG_U, 18, 4, pts)
     want = ex.interpolate(mesh, [b[18:22] for b in data], pts)
     assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_fp32_floors_active_step_within_bound():
+    """FP32 storage with the floors active (chi_floor = 1e-2, alpha_floor =
+    5e-2 on Brill-Lindquist data at dx = 1/8, where chi ~ 1e-3 and alpha ~
+    3e-2 next to the puncture): floors and divisions by chi in double, one RK4
+    step within the FP32 bound of the FP64 oracle on the same float32-rounded
+    data; the floored cells hold float32(floor) and are the oracle's."""
+    mesh = zi.uniform_mesh((2, 2, 2), 16, 4, (-2.0,) * 3, (2.0,) * 3, zi.BC_OUTFLOW)
+    data = zi.brill_lindquist(mesh, [(1.0, (0.0, 0.0, 0.0))])
+    data = [d.astype(np.float32).astype(np.float64) for d in data]
+    p = dict(zi.params_default(6), chi_floor=1e-2, alpha_floor=5e-2)
+    dt = 0.25 * mesh.dx0
+    pk = z().Pack(mesh, p, z().FP32_MIXED)
+    pk.upload(z().REG_U, data)
+    pk.rk4_step(dt, 1)
+    got = pk.download(z().REG_U)
+    om = oracle.OracleMesh(mesh)
+    ro = oracle.rhs(om, p, om.scatter(data))
+    regs = oracle.Registers(om, data)
+    oracle.rk4_steps(regs, p, dt, 1)
+    want = om.interiors(regs.U)
+    for f, fl in ((0, p["chi_floor"]), (18, p["alpha_floor"])):
+        n = sum(int((w[f] == fl).sum()) for w in want)
+        assert n > 0, f
+        for g_, w_ in zip(got, want):
+            assert np.array_equal(g_[f] == np.float64(np.float32(fl)), w_[f] == fl), f
+    bound = dt * rhs_bound(p["fd_order"], mesh.dx0, ro, data)
+    bound = bound + 4 * U32 * np.max([np.abs(w).reshape(22, -1).max(1) for w in want], axis=0)
+    err = np.max([np.abs(g - w).reshape(22, -1).max(1) for g, w in zip(got, want)], axis=0)
+    assert np.all(err <= bound), [(f, err[f], bound[f]) for f in range(22) if err[f] > bound[f]]
+    print("floored FP32 step max err/bound:", float((err / bound).max()))
