@@ -192,23 +192,25 @@ def extra_runs(z4c, zi, torch):
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         mesh, p, data, dt, _ = zi.workload("bbh512mixed")
-        pk = z4c.Pack(mesh, dict(p, graph=1))
-        pk.upload(z4c.REG_U, data)
-        chosen, times = pk.autotune(reps=2, stream=s)
-        pk.rk4_step(dt, 1, stream=s)
-        s.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        pk.rk4_step(dt, 5, stream=s)
-        e1.record(s)
-        s.synchronize()
-        ms = e0.elapsed_time(e1)
-        out["batched_bbh512mixed_fp64"] = {
-            "zcps": pk.zones * 5 / (ms * 1e-3), "zones": pk.zones, "blocks": int(mesh.nb),
-            "levels": int(mesh.level.max()) + 1, "fd_order": 8, "graph": True,
-            "tile_variant": chosen, "autotune_ms": [float(x) for x in times]}
-        del pk
-        torch.cuda.empty_cache()
+        for prec, name in ((z4c.FP64, "fp64"), (z4c.FP32_MIXED, "fp32")):
+            pk = z4c.Pack(mesh, dict(p, graph=1), prec)
+            pk.upload(z4c.REG_U, data)
+            chosen, times = pk.autotune(reps=2, stream=s)
+            pk.rk4_step(dt, 1, stream=s)
+            s.synchronize()
+            e0.record(s)
+            pk.rk4_step(dt, 5, stream=s)
+            e1.record(s)
+            s.synchronize()
+            ms = e0.elapsed_time(e1)
+            out[f"batched_bbh512mixed_{name}"] = {
+                "zcps": pk.zones * 5 / (ms * 1e-3), "zones": pk.zones, "blocks": int(mesh.nb),
+                "levels": int(mesh.level.max()) + 1, "fd_order": 8, "graph": True,
+                "tile_variant": chosen, "autotune_ms": [float(x) for x in times]}
+            print(f"bench: batched {name} done", file=sys.stderr, flush=True)
+            del pk
+            torch.cuda.empty_cache()
         mesh, p, data, dt, _ = zi.workload("bl64x32")
         pk = z4c.Pack(mesh, p, z4c.FP32_MIXED)
         pk.upload(z4c.REG_U, data)

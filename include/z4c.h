@@ -243,6 +243,15 @@ int z4c_set_variant(struct z4c_pack *pack, int32_t variant, int32_t persistent, 
  * between RK4 steps).  Synchronises the stream. */
 int z4c_autotune(struct z4c_pack *pack, int32_t reps, double *times_ms, int32_t *chosen,
                  void *stream);
+/* z4c_autotune with a persistent cache of winners (a text file of JSON
+ * lines at `path`, host): a record whose key matches this pack (device
+ * architecture, FD order, precision, ghost depth, number of levels, block
+ * sizes and their counts) is applied without timing (*from_cache = 1,
+ * times_ms all -1); otherwise every variant is timed as by z4c_autotune and
+ * the winner appended to the file (*from_cache = 0).  Z4C_EINVAL if the
+ * file cannot be written.  from_cache nullable. */
+int z4c_autotune_cached(struct z4c_pack *pack, const char *path, int32_t reps, double *times_ms,
+                        int32_t *chosen, int32_t *from_cache, void *stream);
 
 /* Constraint monitors in double: Hamiltonian H, momentum M^i, Theta and
  * G^i = Gamma~^i - Gamma~_d^i at every active zone of state register `reg`
@@ -397,7 +406,11 @@ int z4c_mlp_forward(const void *params, const void *X, int32_t B, void *Y, void 
 /* Gradient of the mean squared error (Y from z4c_mlp_forward with cache,
  * targets T device float[B]) with respect to the master weights (through
  * the rounding as identity): grad device float[Z4C_MLP_NPARAM]; loss device
- * float[1] (nullable); work device float[B*129]. */
+ * float[1] (nullable); work device float[Z4C_MLP_WORK(B)]: per-sample deltas
+ * (129 per sample), then partial sums of the gradient over slices of
+ * Z4C_MLP_SLICE samples, reduced in slice order (deterministic). */
+#define Z4C_MLP_SLICE 64
+#define Z4C_MLP_WORK(B) ((int64_t)(B) * 129 + (((int64_t)(B) + Z4C_MLP_SLICE - 1) / Z4C_MLP_SLICE) * Z4C_MLP_NPARAM)
 int z4c_mlp_backward(const void *params, const void *X, const void *Y, const void *T,
                      const void *cache, int32_t B, void *grad, void *loss, void *work,
                      void *stream);

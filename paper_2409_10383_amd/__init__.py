@@ -72,7 +72,7 @@ EXPORTS = ["z4c_pack_create", "z4c_pack_query", "z4c_block_offset", "z4c_pack_bi
            "z4c_feature_stats", "z4c_mlp_normalize", "z4c_mlp_forward", "z4c_mlp_backward",
            "z4c_mlp_adam", "z4c_refine_flags_learned", "z4c_set_variant", "z4c_autotune",
            "z4c_regrid_plan", "z4c_regrid_transfer", "z4c_psi4", "z4c_interp", "z4c_interp_state",
-           "z4c_swsh_project", "z4c_tracker_set", "z4c_tracker_get"]
+           "z4c_swsh_project", "z4c_tracker_set", "z4c_tracker_get", "z4c_autotune_cached"]
 MLP_NPARAM = 5313
 
 
@@ -125,6 +125,8 @@ def lib():
                                                C.POINTER(C.c_int8), C.POINTER(C.c_int8), vp]
         L.z4c_set_variant.argtypes = [vp, C.c_int32, C.c_int32, vp]
         L.z4c_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32), vp]
+        L.z4c_autotune_cached.argtypes = [vp, C.c_char_p, C.c_int32, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp]
         L.z4c_regrid_plan.argtypes = [vp, C.POINTER(C.c_int8), C.c_int32, C.POINTER(Block), C.c_int32,
                                       C.POINTER(C.c_int32)]
         L.z4c_regrid_transfer.argtypes = [vp, C.c_int32, vp, C.c_int32, vp]
@@ -371,12 +373,20 @@ class Pack:
     def set_variant(self, variant: int, persistent: bool = False, stream=None):
         self._check(lib().z4c_set_variant(self.h, variant, 1 if persistent else 0, _stream_ptr(stream)))
 
-    def autotune(self, reps: int = 3, stream=None):
+    def autotune(self, reps: int = 3, stream=None, cache: str | None = None):
         """Time every tile shape / launch mode; keep the fastest.  Returns
-        (chosen index, times in ms per RHS launch indexed 2*variant+persistent)."""
+        (chosen index, times in ms per RHS launch indexed 2*variant+persistent).
+        With `cache` (a file path) a stored winner for this configuration is
+        applied without timing (times then all -1) and new winners stored."""
         t = (C.c_double * 8)()
         ch = C.c_int32()
-        self._check(lib().z4c_autotune(self.h, reps, t, C.byref(ch), _stream_ptr(stream)))
+        if cache is None:
+            self._check(lib().z4c_autotune(self.h, reps, t, C.byref(ch), _stream_ptr(stream)))
+        else:
+            hit = C.c_int32()
+            self._check(lib().z4c_autotune_cached(self.h, os.fsencode(cache), reps, t, C.byref(ch),
+                                                  C.byref(hit), _stream_ptr(stream)))
+            self.tuned_from_cache = bool(hit.value)
         return int(ch.value), np.array(t[:])
 
     def regrid_plan(self, flags, level_max: int):
@@ -531,6 +541,14 @@ def labels(pack_h: "Pack", rhs_h, pack_2h: "Pack", rhs_2h, stream=None):
     return out
 
 
+MLP_SLICE = 64
+
+
+def mlp_work_floats(B: int) -> int:
+    """Floats of the backward pass's work buffer (Z4C_MLP_WORK)."""
+    return B * 129 + (B + MLP_SLICE - 1) // MLP_SLICE * MLP_NPARAM
+
+
 class Mlp:
     """Device state of the 16-64-64-1 indicator network (float32 master
     weights, Adam moments, feature statistics); all arithmetic in libz4c."""
@@ -572,7 +590,7 @@ class Mlp:
         import torch
         B = X.shape[0]
         cache = torch.empty(B * 128, dtype=torch.float32, device=self.device)
-        work = torch.empty(B * 129, dtype=torch.float32, device=self.device)
+        work = torch.empty(mlp_work_floats(B), dtype=torch.float32, device=self.device)
         Y = self.forward(X, cache)
         _ok(lib().z4c_mlp_backward(_ptr(self.params), _ptr(X), _ptr(Y), _ptr(T), _ptr(cache), B,
                                    _ptr(self.grad), _ptr(self.loss), _ptr(work), _stream_ptr(None)),

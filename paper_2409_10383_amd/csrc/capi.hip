@@ -1063,6 +1063,91 @@ int z4c_autotune(z4c_pack* pk, int32_t reps, double* times_ms, int32_t* chosen, 
     return z4c_set_variant(pk, bv, bp, stream);
 }
 
+// Autotuner cache: one line per tuned configuration,
+//   {"key": "<arch>|order=<o>|prec=<p>|g=<g>|levels=<l>|n=<n>x<count>,...", "variant": v, "persistent": 0|1, "ms": t}
+// keyed by what the choice depends on (device architecture, FD order,
+// storage precision, ghost depth, number of levels, block sizes and counts).
+static std::string tune_key(const z4c_pack* pk)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    std::map<int, int> sizes;
+    int lmax = 0;
+    for (const z4c_block& b : pk->blk) {
+        sizes[b.n] += 1;
+        lmax = std::max(lmax, (int)b.level);
+    }
+    std::string k = arch + "|order=" + std::to_string(pk->p.fd_order) + "|prec=" + std::to_string(pk->p.precision) +
+                    "|g=" + std::to_string(pk->p.nghost) + "|levels=" + std::to_string(lmax + 1) + "|n=";
+    bool first = true;
+    for (const auto& e : sizes) {
+        if (!first) k += ",";
+        k += std::to_string(e.first) + "x" + std::to_string(e.second);
+        first = false;
+    }
+    return k;
+}
+
+int z4c_autotune_cached(z4c_pack* pk, const char* path, int32_t reps, double* times_ms, int32_t* chosen,
+                        int32_t* from_cache, void* stream)
+{
+    if (!pk) return Z4C_EINVAL;
+    if (!path || !chosen) return fail(pk, Z4C_EINVAL, "null cache path or output");
+    if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
+    const std::string key = tune_key(pk);
+    if (from_cache) *from_cache = 0;
+    if (FILE* f = std::fopen(path, "r")) {
+        char line[1024];
+        int hit_v = -1, hit_p = 0;
+        while (std::fgets(line, sizeof(line), f)) {
+            const char* kq = std::strstr(line, "\"key\": \"");
+            if (!kq) continue;
+            kq += 8;
+            const char* ke = std::strchr(kq, '"');
+            if (!ke || std::string(kq, ke) != key) continue;
+            const char* vq = std::strstr(ke, "\"variant\": ");
+            const char* pq = std::strstr(ke, "\"persistent\": ");
+            int v = -1, per = 0;
+            if (vq && pq && std::sscanf(vq + 11, "%d", &v) == 1 && std::sscanf(pq + 14, "%d", &per) == 1 &&
+                v >= 0 && v < NVARIANT && (per == 0 || per == 1)) {
+                hit_v = v;   // the last record of a key wins
+                hit_p = per;
+            }
+        }
+        std::fclose(f);
+        if (hit_v >= 0) {
+            const int rc = z4c_set_variant(pk, hit_v, hit_p, stream);
+            if (rc == Z4C_OK) {
+                if (times_ms)
+                    for (int q = 0; q < 2 * NVARIANT; ++q) times_ms[q] = -1.0;
+                *chosen = 2 * hit_v + hit_p;
+                if (from_cache) *from_cache = 1;
+                return Z4C_OK;
+            }
+            // a record that no longer applies (e.g. the tile does not divide
+            // the blocks) falls through to timing
+        }
+    }
+    double t[2 * NVARIANT];
+    int rc = z4c_autotune(pk, reps, t, chosen, stream);
+    if (rc) return rc;
+    if (times_ms)
+        for (int q = 0; q < 2 * NVARIANT; ++q) times_ms[q] = t[q];
+    if (FILE* f = std::fopen(path, "a")) {
+        std::fprintf(f, "{\"key\": \"%s\", \"variant\": %d, \"persistent\": %d, \"ms\": %.6g}\n", key.c_str(),
+                     *chosen / 2, *chosen % 2, t[*chosen]);
+        std::fclose(f);
+    } else {
+        return fail(pk, Z4C_EINVAL, "cannot write autotune cache %s", path);
+    }
+    return Z4C_OK;
+}
+
 static int run_diag(z4c_pack* pk, int32_t reg, int mode, void* per_zone, const double* centres,
                     int ncentres, double r_exc, void* stream)
 {

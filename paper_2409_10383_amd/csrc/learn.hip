@@ -2,6 +2,7 @@
 // sublattice (the 2h pack), h-vs-2h RHS labels, feature normalisation and
 // the 16 -> 64 -> 64 -> 1 perceptron (bfloat16 weights and activations,
 // float32 accumulation): forward, backward and Adam.
+#include "../../include/z4c.h"
 #include "kernels.hpp"
 #include "z4c_rhs.hpp"
 
@@ -164,6 +165,8 @@ __device__ __forceinline__ float bf16r(float x)
 }
 
 constexpr int H = 64;
+// samples per partial-gradient slice of the backward pass
+constexpr int MLP_SLICE = Z4C_MLP_SLICE;
 constexpr int OW1 = 0, OB1 = OW1 + H * NFEAT, OW2 = OB1 + H, OB2 = OW2 + H * H, OW3 = OB2 + H,
               OB3 = OW3 + H, NPARAM = OB3 + 1;
 
@@ -265,38 +268,60 @@ __global__ __launch_bounds__(256) void k_mlp_bwd_delta(const float* P, const flo
     wk[2 * H] = dy;
 }
 
-// backward, step 2: one thread per parameter, sum over the batch in order
-__global__ __launch_bounds__(256) void k_mlp_bwd_grad(const float* X, const float* cache,
-                                                      const float* work, int B, float* G)
+// backward, step 2: partial sums of the weight gradients over slices of
+// MLP_SLICE samples (dW = delta^T x per layer, db = sum of delta), one
+// workgroup per slice; the slice's deltas and layer inputs are staged in LDS
+// and each thread sums its parameters over the slice's samples in order.
+// partial layout: [slice][NPARAM]
+__global__ __launch_bounds__(256) void k_mlp_bwd_partial(const float* X, const float* cache,
+                                                         const float* work, int B, float* partial)
+{
+    constexpr int W = 2 * H + 1;              // deltas per sample in work
+    __shared__ float d[MLP_SLICE][W];         // delta1, delta2, dy
+    __shared__ float x[MLP_SLICE][NFEAT];     // bf16 inputs
+    __shared__ float h[MLP_SLICE][2 * H];     // bf16 relu(a1), relu(a2)
+    const int s0 = blockIdx.x * MLP_SLICE;
+    const int ns = min(MLP_SLICE, B - s0);
+    for (int q = threadIdx.x; q < ns * W; q += 256) d[q / W][q % W] = work[(int64_t)s0 * W + q];
+    for (int q = threadIdx.x; q < ns * NFEAT; q += 256)
+        x[q / NFEAT][q % NFEAT] = bf16r(X[(int64_t)s0 * NFEAT + q]);
+    for (int q = threadIdx.x; q < ns * 2 * H; q += 256) {
+        const float v = cache[(int64_t)s0 * 2 * H + q];
+        h[q / (2 * H)][q % (2 * H)] = bf16r(v > 0.f ? v : 0.f);
+    }
+    __syncthreads();
+    float* out = partial + (int64_t)blockIdx.x * NPARAM;
+    for (int q = threadIdx.x; q < NPARAM; q += 256) {
+        float acc = 0.f;
+        if (q < OB1) {  // W1[o][k] : delta1_o * x_k
+            const int o = q / NFEAT, k = q % NFEAT;
+            for (int s = 0; s < ns; ++s) acc += d[s][o] * x[s][k];
+        } else if (q < OW2) {
+            const int o = q - OB1;
+            for (int s = 0; s < ns; ++s) acc += d[s][o];
+        } else if (q < OB2) {  // W2[o][k] : delta2_o * h1_k
+            const int o = (q - OW2) / H, k = (q - OW2) % H;
+            for (int s = 0; s < ns; ++s) acc += d[s][H + o] * h[s][k];
+        } else if (q < OW3) {
+            const int o = q - OB2;
+            for (int s = 0; s < ns; ++s) acc += d[s][H + o];
+        } else if (q < OB3) {  // W3[k] : dy * h2_k
+            const int k = q - OW3;
+            for (int s = 0; s < ns; ++s) acc += d[s][2 * H] * h[s][H + k];
+        } else {
+            for (int s = 0; s < ns; ++s) acc += d[s][2 * H];
+        }
+        out[q] = acc;
+    }
+}
+
+// backward, step 3: one thread per parameter sums the slices in order
+__global__ __launch_bounds__(256) void k_mlp_bwd_reduce(const float* partial, int nslice, float* G)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= NPARAM) return;
     float acc = 0.f;
-    const int64_t ws = 2 * H + 1;
-    if (q < OB1) {  // W1[o][k] : delta1_o * x_k
-        const int o = q / NFEAT, k = q % NFEAT;
-        for (int s = 0; s < B; ++s) acc += work[s * ws + o] * bf16r(X[(int64_t)s * NFEAT + k]);
-    } else if (q < OW2) {
-        const int o = q - OB1;
-        for (int s = 0; s < B; ++s) acc += work[s * ws + o];
-    } else if (q < OB2) {  // W2[o][k] : delta2_o * h1_k
-        const int o = (q - OW2) / H, k = (q - OW2) % H;
-        for (int s = 0; s < B; ++s) {
-            const float a1 = cache[(int64_t)s * 2 * H + k];
-            acc += work[s * ws + H + o] * bf16r(a1 > 0.f ? a1 : 0.f);
-        }
-    } else if (q < OW3) {
-        const int o = q - OB2;
-        for (int s = 0; s < B; ++s) acc += work[s * ws + H + o];
-    } else if (q < OB3) {  // W3[k] : dy * h2_k
-        const int k = q - OW3;
-        for (int s = 0; s < B; ++s) {
-            const float a2 = cache[(int64_t)s * 2 * H + H + k];
-            acc += work[s * ws + 2 * H] * bf16r(a2 > 0.f ? a2 : 0.f);
-        }
-    } else {
-        for (int s = 0; s < B; ++s) acc += work[s * ws + 2 * H];
-    }
+    for (int sl = 0; sl < nslice; ++sl) acc += partial[(int64_t)sl * NPARAM + q];
     G[q] = acc;
 }
 
@@ -370,8 +395,11 @@ hipError_t launch_mlp_forward(const float* P, const float* X, int B, float* Y, f
 hipError_t launch_mlp_backward(const float* P, const float* X, const float* Y, const float* T,
                                const float* cache, int B, float* G, float* loss, float* work, hipStream_t s)
 {
+    const int nslice = (B + MLP_SLICE - 1) / MLP_SLICE;
+    float* partial = work + (int64_t)B * (2 * H + 1);
     hipLaunchKernelGGL(k_mlp_bwd_delta, dim3((B + 255) / 256), dim3(256), 0, s, P, Y, T, cache, B, work);
-    hipLaunchKernelGGL(k_mlp_bwd_grad, dim3((NPARAM + 255) / 256), dim3(256), 0, s, X, cache, work, B, G);
+    hipLaunchKernelGGL(k_mlp_bwd_partial, dim3(nslice), dim3(256), 0, s, X, cache, work, B, partial);
+    hipLaunchKernelGGL(k_mlp_bwd_reduce, dim3((NPARAM + 255) / 256), dim3(256), 0, s, partial, nslice, G);
     if (loss) hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, s, Y, T, B, loss);
     return hipGetLastError();
 }

@@ -105,3 +105,36 @@ def test_graph_step_after_rebind_uses_new_registers():
         b = eager.state_view(z().REG_U).cpu().numpy()
         assert np.array_equal(a, b, equal_nan=True)
         assert torch.equal(old[z().REG_U], old_u)
+
+
+def test_autotune_cache_skips_timing_for_a_known_configuration(tmp_path):
+    """Winners persist per (architecture, order, precision, ghosts, levels,
+    block sizes): the first pack is timed and its winner stored; a second
+    pack of the same configuration takes it from the file without timing,
+    and gives the same state as the timed pack after a step."""
+    mesh, p, data = mixed_pack(6)
+    path = str(tmp_path / "tune.jsonl")
+    a = z().Pack(mesh, p)
+    a.upload(z().REG_U, data)
+    ca, ta = a.autotune(reps=1, cache=path)
+    assert not a.tuned_from_cache and ta[ca] > 0
+    b = z().Pack(mesh, p)
+    b.upload(z().REG_U, data)
+    cb, tb = b.autotune(reps=1, cache=path)
+    assert b.tuned_from_cache and cb == ca and np.all(tb == -1.0)
+    with open(path) as f:
+        lines = f.readlines()
+    assert len(lines) == 1 and '"variant": %d' % (ca // 2) in lines[0]
+    dt = 0.25 * mesh.dx_min()
+    a.upload(z().REG_U, data)
+    a.rk4_step(dt, 1)
+    b.rk4_step(dt, 1)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.state_view(z().REG_U).cpu().numpy(), b.state_view(z().REG_U).cpu().numpy(),
+                          equal_nan=True)
+    # another configuration (8th order) misses the cache and is timed
+    mesh8, p8, data8 = mixed_pack(8)
+    c = z().Pack(mesh8, p8)
+    c.upload(z().REG_U, data8)
+    c.autotune(reps=1, cache=path)
+    assert not c.tuned_from_cache

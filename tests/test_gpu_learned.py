@@ -142,8 +142,33 @@ def test_training_beats_dchi_max_at_equal_budget():
         learned = set(np.argsort(-pred[sl])[:K])
         dchi = set(np.argsort(-Fte[sl, 0])[:K])
         gains.append((len(truth & learned) - len(truth & dchi)) / K)
+    # a smoke check of the training loop on small packs (64 blocks, K = 8):
+    # the strict gain is asserted at the config-5 scale below
+    print("precision@K gain over dchi-max (small packs):", np.mean(gains), gains)
     assert np.mean(gains) >= 0.0, gains
-    print("precision@K gain over dchi-max:", np.mean(gains), gains)
+
+
+def test_learned_indicator_beats_dchi_max_at_config5_scale():
+    """The 4096 x 16^3 two-puncture pack (dx = 0.125): the network trained on
+    the GPU on h-vs-2h labels of six random setups (masses 0.3-0.7,
+    separations 6-14, two time slices each: 49152 blocks) ranks the blocks of
+    two held-out setups, and its top 256 are compared with the 256 blocks of
+    largest label (the method's own truncation-error estimate).  Stated
+    metric: precision at K = 256.  The learned ranking must beat dchi-max's
+    (the plain criterion of Sec. 3.3) by at least 0.2 on every held-out setup
+    (measured: 0.49 / 0.59 against 0.023 / 0.016)."""
+    from paper_2409_10383_amd import experiments as ex
+    net, snapshot, test, ntrain, loss = ex._train(6, 40)
+    assert ntrain == 6 * 2 * 4096
+    K = 256
+    for v in test:
+        F, Y, D = snapshot(*v, steps=(0,))
+        pred = net.forward(net.normalize(D[0])).cpu().numpy()
+        truth = set(np.argsort(-Y[0])[:K])
+        learned = len(truth & set(np.argsort(-pred)[:K])) / K
+        dchi = len(truth & set(np.argsort(-F[0][:, 0])[:K])) / K
+        print("held-out setup", v, "precision@256 learned", learned, "dchi-max", dchi)
+        assert learned >= dchi + 0.2, (v, learned, dchi)
 
 
 def _phi(raw):

@@ -13,8 +13,8 @@ is measured.
   Prolonged ghost values are 5th-order accurate, and the Ricci terms take
   second differences of them, so the right-hand side next to the interface
   errs at O(H^3) in a layer a few cells wide and the volume-integrated
-  error converges at 4th order.  That is asserted, together with a bound
-  on how far the refined run may exceed the uniform one."""
+  error converges at 4th order.  That is asserted, and the refined run is
+  compared with the oracle zone by zone."""
 import math
 
 import numpy as np
@@ -98,13 +98,36 @@ def refined_corner(n):
 
 
 def test_refined_corner_interface_order():
+    """The volume-integrated error of the refined-corner run converges at the
+    order the interface sets (reading R22): the RHS errs at O(H^3) in a layer
+    a few cells wide next to the interface (pinned on the oracle in
+    test_oracle_regrid.py), i.e. O(H^3 h) = O(H^4) integrated.  Measured rates
+    4.2, 4.1; the refined run's error is 1.8-2.4x the uniform run's at the
+    same coarse resolution (printed; Sec. 4.1 reports it lower)."""
     ns = (16, 32, 48)
     ref = [evolve(refined_corner(n)) for n in ns]
     rates = [rate(ref[i], ref[i + 1], ns[i], ns[i + 1]) for i in range(2)]
     uni = evolve(cube(32))
-    print("L1_RMS refined corner", ref, "rates", rates, "uniform 32^3", uni)
-    assert all(r > 3.7 for r in rates), (ref, rates)
-    assert ref[1] < 3.0 * uni, (ref[1], uni)
+    print("L1_RMS refined corner", ref, "rates", rates, "uniform 32^3", uni, "ratio", ref[1] / uni)
+    assert all(3.6 < r < 4.6 for r in rates), (ref, rates)
+
+
+def test_refined_corner_steps_match_oracle():
+    """The refined-corner linear wave (Sec. 4.1) stepped on the GPU and by
+    the oracle: five RK4 steps, every zone of every field at the evolved-state
+    bar (per field, with the oracle's own rounding floor)."""
+    from _parity import assert_parity, oracle_steps
+    mesh = refined_corner(16)
+    fn = an.linear_wave_diagonal(1e-6, 1.0)
+    data = [an.adm_to_z4c(fn, 0.0, *mesh.grid(b)) for b in range(mesh.nb)]
+    p = zi.params_default(6)
+    dt = 0.25 * mesh.dx_min()
+    pk = z().Pack(mesh, p)
+    pk.upload(z().REG_U, data)
+    pk.rk4_step(dt, 5)
+    torch.cuda.synchronize()
+    want, floor = oracle_steps(mesh, p, data, dt, 5)
+    assert_parity(pk.download(z().REG_U), want, what="refined-corner wave, 5 steps", floor=floor)
 
 
 def evolve_amplitude(n, A, cfl=0.0625):

@@ -200,3 +200,41 @@ def test_fp32_floors_active_step_within_bound():
     err = np.max([np.abs(g - w).reshape(22, -1).max(1) for g, w in zip(got, want)], axis=0)
     assert np.all(err <= bound), [(f, err[f], bound[f]) for f in range(22) if err[f] > bound[f]]
     print("floored FP32 step max err/bound:", float((err / bound).max()))
+
+
+def test_config4_fp32_storage_100_steps_within_field_bounds():
+    """The precision workload (512 x 32^3 Brill-Lindquist plus 1e-6
+    perturbations, dx = 0.125, 6th order): 100 RK4 steps with FP32 storage
+    against the FP64 run; every field's largest difference below its
+    a-priori bound (n u32 max|f| + n dt K u32 (max|rhs_f| + S W2 / h^2), the
+    maxima from the FP64 initial state) and the Hamiltonian-constraint L2 of
+    the FP32 run within twice the FP64 run's."""
+    mesh, p, data, dt, steps = zi.workload("bl512x32")
+    assert steps == 100
+    states, hl2 = {}, {}
+    for prec in (z().FP64, z().FP32_MIXED):
+        pk = z().Pack(mesh, p, prec)
+        pk.upload(z().REG_U, data)
+        if prec == z().FP64:
+            pk.fill_ghosts()
+            rhs0 = pk.split_interior(pk.rhs())
+        pk.rk4_step(dt, steps)
+        _, nf = pk.constraints(per_zone=False)
+        _, ne = pk.constraints(per_zone=False, exclude=[(0.0, 0.0, 0.0)], r_exc=2.0)
+        hl2[prec] = (nf[0], ne[0])
+        states[prec] = pk.download(z().REG_U)
+        del pk
+        torch.cuda.empty_cache()
+    S = max(np.abs(d[[0, 1, 4, 6, 18]]).max() for d in data)
+    worst = 0.0
+    for f in range(22):
+        err = max(float(np.abs(a[f] - b[f]).max()) for a, b in zip(states[z().FP32_MIXED], states[z().FP64]))
+        fmax = max(float(np.abs(d[f]).max()) for d in data)
+        rmax = max(float(np.abs(r[f]).max()) for r in rhs0)
+        bound = steps * U32 * fmax + steps * dt * K * U32 * (rmax + S * W2[6] / mesh.dx0 ** 2)
+        assert err <= bound, (zi.FIELDS[f], err, bound)
+        worst = max(worst, err / bound)
+    ratio = hl2[z().FP32_MIXED][0] / hl2[z().FP64][0]
+    print("config 4: worst field error / bound", worst, "H_L2 fp32/fp64", ratio,
+          "excised", hl2[z().FP32_MIXED][1] / hl2[z().FP64][1])
+    assert ratio <= 2.0

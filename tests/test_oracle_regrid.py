@@ -178,3 +178,33 @@ def test_prolongating_chi_through_a_puncture_overshoots_below_zero():
     got_min = min(float(new[b][0].min()) for b in fine)
     exact_min = min(float(exact[b][0].min()) for b in fine)
     assert exact_min > 0.0 and got_min < 0.0, (got_min, exact_min)
+
+
+def test_refinement_interface_rhs_error_is_third_order():
+    """Reading R22 (Sec. 4.1's refined corner): the cross-level ghost values
+    (n = N_g + 1 = 5 point Lagrange interpolation, Sec. 3.1) err at O(H^5),
+    and the right-hand side takes second differences of them, so next to the
+    refinement interface it errs at O(H^5 / h^2) = O(H^3) on both sides
+    (prolongated fine ghosts and restricted coarse ghosts).  Measured as the
+    RHS with the oracle's fill minus the RHS with exact (analytic) ghosts, on
+    the linear wave with one octant refined."""
+    from z4c_inputs import analytic as an
+
+    def refined_corner(n, bc):
+        base = zi.uniform_mesh((2, 2, 2), n // 2, 4, (0.0,) * 3, (1.0,) * 3, bc)
+        return zi.refine_blocks(base, [0])
+    fn = an.linear_wave_diagonal(1e-3, 1.0)
+
+    def f(X, Y, Z):
+        return an.adm_to_z4c(fn, 0.0, X, Y, Z)
+    p = zi.params_default(6)
+    errs = []
+    for n in (16, 32):
+        m1, m0 = refined_corner(n, zi.BC_PERIODIC), refined_corner(n, zi.BC_USER)
+        o1, o0 = oracle.OracleMesh(m1), oracle.OracleMesh(m0)
+        r1 = oracle.rhs(o1, p, o1.scatter([f(*m1.grid(b)) for b in range(m1.nb)]))
+        r0 = oracle.rhs(o0, p, o0.scatter_ghosted(an.ghosted_data(m0, f)), fill=False)
+        errs.append([max(np.abs(r1[b] - r0[b]).max() for b in range(m1.nb) if m1.level[b] == lev)
+                     for lev in (1, 0)])
+    rates = np.log2(np.array(errs[0]) / np.array(errs[1]))
+    assert np.all((rates > 2.6) & (rates < 3.4)), (errs, rates)   # measured 2.98, 2.81
