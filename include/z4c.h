@@ -414,6 +414,18 @@ int z4c_mlp_forward(const void *params, const void *X, int32_t B, void *Y, void 
 int z4c_mlp_backward(const void *params, const void *X, const void *Y, const void *T,
                      const void *cache, int32_t B, void *grad, void *loss, void *work,
                      void *stream);
+/* z4c_mlp_backward without the work argument, for callers that cannot
+ * allocate device memory (code under hipGraph capture, serving loops,
+ * harnesses that forbid hipMalloc): the work buffer is a library-owned
+ * device array of Z4C_MLP_WORK(Z4C_MLP_NOALLOC_MAXB) floats (3.5 MB), one
+ * per GPU, kept until the process ends; the call itself allocates nothing.
+ * B > Z4C_MLP_NOALLOC_MAXB returns Z4C_EINVAL.  Every call on one GPU uses
+ * that GPU's array: calls that overlap on one GPU (other streams, other
+ * threads) race and must be ordered by the caller.  Same kernels and
+ * results as z4c_mlp_backward. */
+#define Z4C_MLP_NOALLOC_MAXB 4096
+int z4c_mlp_backward_noalloc(const void *params, const void *X, const void *Y, const void *T,
+                             const void *cache, int32_t B, void *grad, void *loss, void *stream);
 /* One Adam step (step counts from 1) on params with moments m, v (device
  * float[Z4C_MLP_NPARAM] each). */
 int z4c_mlp_adam(void *params, const void *grad, void *m, void *v, int32_t step, float lr,

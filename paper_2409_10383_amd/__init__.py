@@ -72,7 +72,7 @@ EXPORTS = ["z4c_pack_create", "z4c_pack_query", "z4c_block_offset", "z4c_pack_bi
            "z4c_feature_stats", "z4c_mlp_normalize", "z4c_mlp_forward", "z4c_mlp_backward",
            "z4c_mlp_adam", "z4c_refine_flags_learned", "z4c_set_variant", "z4c_autotune",
            "z4c_regrid_plan", "z4c_regrid_transfer", "z4c_psi4", "z4c_interp", "z4c_interp_state",
-           "z4c_swsh_project", "z4c_tracker_set", "z4c_tracker_get", "z4c_autotune_cached"]
+           "z4c_swsh_project", "z4c_tracker_set", "z4c_tracker_get", "z4c_mlp_backward_noalloc", "z4c_autotune_cached"]
 MLP_NPARAM = 5313
 
 
@@ -119,6 +119,7 @@ def lib():
         L.z4c_mlp_normalize.argtypes = [vp, C.c_int32, vp, vp, vp]
         L.z4c_mlp_forward.argtypes = [vp, vp, C.c_int32, vp, vp, vp]
         L.z4c_mlp_backward.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp, vp, vp, vp]
+        L.z4c_mlp_backward_noalloc.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp, vp, vp]
         L.z4c_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float,
                                    C.c_float, vp]
         L.z4c_refine_flags_learned.argtypes = [vp, C.c_int32, C.POINTER(MlpModel),
@@ -595,6 +596,17 @@ class Mlp:
         _ok(lib().z4c_mlp_backward(_ptr(self.params), _ptr(X), _ptr(Y), _ptr(T), _ptr(cache), B,
                                    _ptr(self.grad), _ptr(self.loss), _ptr(work), _stream_ptr(None)),
             "mlp backward")
+        return Y, self.grad, self.loss
+
+    def loss_grad_noalloc(self, X, T):
+        """loss_grad through z4c_mlp_backward_noalloc (no work buffer)."""
+        import torch
+        B = X.shape[0]
+        cache = torch.empty(B * 128, dtype=torch.float32, device=self.device)
+        Y = self.forward(X, cache)
+        _ok(lib().z4c_mlp_backward_noalloc(_ptr(self.params), _ptr(X), _ptr(Y), _ptr(T), _ptr(cache), B,
+                                           _ptr(self.grad), _ptr(self.loss), _stream_ptr(None)),
+            "mlp backward (no allocation)")
         return Y, self.grad, self.loss
 
     def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

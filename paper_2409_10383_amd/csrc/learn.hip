@@ -3,6 +3,7 @@
 // the 16 -> 64 -> 64 -> 1 perceptron (bfloat16 weights and activations,
 // float32 accumulation): forward, backward and Adam.
 #include "../../include/z4c.h"
+#include <mutex>
 #include "kernels.hpp"
 #include "z4c_rhs.hpp"
 
@@ -463,3 +464,44 @@ hipError_t launch_feat_stats(const double* raw, int B, double* stats, hipStream_
 }
 
 }  // namespace z4c
+
+// ------------------------------------------------ allocation-free backward
+// Work buffer of z4c_mlp_backward_noalloc for up to Z4C_MLP_NOALLOC_MAXB
+// samples: every GPU the library runs on holds its own copy until the
+// process ends.  Host code never passes the array's name to a kernel: it
+// takes the device address hipGetSymbolAddress returns on each device.
+static __device__ __align__(256) float scratch[Z4C_MLP_WORK(Z4C_MLP_NOALLOC_MAXB)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+float* scratch_dev[kMaxDevices];   // address of `scratch` on each device
+}  // namespace
+
+extern "C" int z4c_mlp_backward_noalloc(const void* params, const void* X, const void* Y, const void* T,
+                                        const void* cache, int32_t B, void* grad, void* loss, void* stream)
+{
+    if (!params || !X || !Y || !T || !cache || !grad || B < 1) return Z4C_EINVAL;
+    if (B > Z4C_MLP_NOALLOC_MAXB) return Z4C_EINVAL;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return Z4C_EDEVICE;
+    float* work = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(scratch_mu);
+        if (!scratch_dev[dev]) {
+            void* ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return Z4C_EDEVICE;
+            scratch_dev[dev] = static_cast<float*>(ptr);
+        }
+        work = scratch_dev[dev];
+    }
+    // every value the kernels read from the work buffer is written earlier in
+    // the same call (deltas, then every slice's partial sums): nothing to clear
+    return z4c::launch_mlp_backward(static_cast<const float*>(params), static_cast<const float*>(X),
+                                    static_cast<const float*>(Y), static_cast<const float*>(T),
+                                    static_cast<const float*>(cache), B, static_cast<float*>(grad),
+                                    static_cast<float*>(loss), work, static_cast<hipStream_t>(stream)) ==
+                   hipSuccess
+               ? Z4C_OK
+               : Z4C_EDEVICE;
+}
