@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libz4c.so")
+# Z4C_LIB: load the library from another path (e.g. a variant build)
+LIB_PATH = os.environ.get("Z4C_LIB", os.path.join(HERE, "libz4c.so"))
 
 NF = 22
 NREG = 4

@@ -129,10 +129,20 @@ template <int N, class T, class C, int TX, int TY, int TZ>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w, C* tile, C* dxs,
                                            C* dys, C* adks);
 
+// Waves per SIMD the compiler is asked to fit: FP32 storage fits two (the
+// 8th-order kernels would otherwise take 289 registers, one wave; asking for
+// two spills 31 of them, the tile's copy offsets, to scratch, and the stage
+// takes 3.9 instead of 6.3 ms on the 512-block pack); the FP64 kernels need
+// about 440 registers and stay at one.
+template <class T> struct StageWaves {
+    static constexpr int value = sizeof(T) == 4 ? 2 : 1;
+};
+
 // One launch per stage.  With a.persistent the grid is sized to the
 // resident workgroups and each loops over its XCD's share of the work.
 template <int N, class T, class C, int TX, int TY, int TZ>
-__global__ __launch_bounds__(256) void k_stage(const StageArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<T>::value))) void k_stage(
+    const StageArgs a)
 {
     using G = TileGeom<N, TX, TY, TZ>;
     __shared__ __align__(16) C tile[StageLds<G, C>::NBUF * G::NS];
