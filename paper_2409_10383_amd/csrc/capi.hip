@@ -177,11 +177,21 @@ int build_xlevel(z4c_pack* pk)
     const int nb = (int)pk->blk.size();
     pk->img_off.assign(nb, -1);
     // image rows (z-plane * m + y) some transfer reads, per source block
+    // and the range of coarse x each such row needs
     std::vector<std::vector<uint8_t>> img_rows(nb);
+    std::vector<std::vector<int16_t>> img_xlo(nb), img_xhi(nb);
     auto need_row = [&](int F, int64_t ic) {
         const int64_t m = pk->blk[F].n / 2;
-        if (img_rows[F].empty()) img_rows[F].assign((size_t)(m * m), 0);
-        img_rows[F][(size_t)(ic / m)] = 1;
+        if (img_rows[F].empty()) {
+            img_rows[F].assign((size_t)(m * m), 0);
+            img_xlo[F].assign((size_t)(m * m), (int16_t)m);
+            img_xhi[F].assign((size_t)(m * m), (int16_t)-1);
+        }
+        const size_t row = (size_t)(ic / m);
+        const int16_t x = (int16_t)(ic % m);
+        img_rows[F][row] = 1;
+        img_xlo[F][row] = std::min(img_xlo[F][row], x);
+        img_xhi[F][row] = std::max(img_xhi[F][row], x);
     };
     pk->img_fstride.assign(nb, 0);
     // coarse image of fine block F (allocated on first use)
@@ -339,21 +349,25 @@ int build_xlevel(z4c_pack* pk)
         const std::vector<uint8_t>& need = img_rows[F];
         for (int kz = 0; kz < m; ++kz)
             for (int y0 = 0; y0 < m; y0 += cy) {
-                int lo = -1, hi = -1;
+                int lo = -1, hi = -1, xlo = m, xhi = -1;
                 for (int y = y0; y < std::min(y0 + cy, m); ++y)
                     if (need[(size_t)kz * m + y]) {
                         if (lo < 0) lo = y;
                         hi = y;
+                        xlo = std::min<int>(xlo, img_xlo[F][(size_t)kz * m + y]);
+                        xhi = std::max<int>(xhi, img_xhi[F][(size_t)kz * m + y]);
                     }
                 if (lo < 0) continue;
                 ImageSlice sl;
+                std::memset(&sl, 0, sizeof(sl));
                 sl.img = pk->img_off[F];
                 sl.block = F;
                 sl.fstride = pk->img_fstride[F];
                 sl.kz = (int16_t)kz;
                 sl.y0 = (int16_t)lo;
                 sl.ny = (int16_t)(hi - lo + 1);
-                sl.pad = 0;
+                sl.x0 = (int16_t)xlo;
+                sl.nx = (int16_t)(xhi - xlo + 1);
                 pk->islice.push_back(sl);
             }
     }

@@ -91,7 +91,9 @@ __global__ __launch_bounds__(256) void k_restrict_image(const XlevelArgs a)
 {
     __shared__ double X[RI_XMAX];
     __shared__ double Y[RI_YMAX];
-    const ImageSlice sl = a.islice[blockIdx.x];
+    const int64_t w = xcd_run(blockIdx.x, a.nislice);
+    if (w >= a.nislice) return;
+    const ImageSlice sl = a.islice[w];
     const BlockDev F = a.blocks[sl.block];
     const int n = F.n, m = n >> 1, np = NP ? NP : a.npts, E = F.E, g = (E - n) >> 1;
     const int t = threadIdx.x, ny = sl.ny;
@@ -103,13 +105,15 @@ __global__ __launch_bounds__(256) void k_restrict_image(const XlevelArgs a)
     const T* base = (const T*)a.reg + F.off + ((int64_t)(oz + g) * E + (oy0 + g)) * E + g;
     T* img = (T*)a.image + sl.img;
     const double* wz = a.rw + 8 * dz;
-    const int nx = m * R * np, nyq = m * ny * np, nz = m * ny;
+    // coarse columns x0 .. x0 + cx - 1 only (those some transfer reads)
+    const int x0 = sl.x0, cx = sl.nx;
+    const int nxq = cx * R * np, nyq = cx * ny * np, nz = cx * ny;
     for (int f = 0; f < NF; ++f) {
         const T* p = base + (int64_t)f * F.slab;
-        for (int q = t; q < nx; q += 256) {
-            const int kx = q % m, r = (q / m) % R, pz = q / (m * R);
+        for (int q = t; q < nxq; q += 256) {
+            const int kx = q % cx, r = (q / cx) % R, pz = q / (cx * R);
             int ox, dx;
-            rwin(kx, n, np, ox, dx);
+            rwin(x0 + kx, n, np, ox, dx);
             const T* row = p + ((int64_t)pz * E + r) * E + ox;
             const double* wx = a.rw + 8 * dx;
             double s = 0.0;
@@ -119,33 +123,34 @@ __global__ __launch_bounds__(256) void k_restrict_image(const XlevelArgs a)
         }
         __syncthreads();
         for (int q = t; q < nyq; q += 256) {
-            const int kx = q % m, cy = (q / m) % ny, pz = q / (m * ny);
+            const int kx = q % cx, cy = (q / cx) % ny, pz = q / (cx * ny);
             int oy, dy;
             rwin(sl.y0 + cy, n, np, oy, dy);
             const double* wy = a.rw + 8 * dy;
             double s = 0.0;
 #pragma unroll
-            for (int jy = 0; jy < np; ++jy) s += wy[jy] * X[(pz * R + (oy - oy0 + jy)) * m + kx];
+            for (int jy = 0; jy < np; ++jy) s += wy[jy] * X[(pz * R + (oy - oy0 + jy)) * cx + kx];
             Y[q] = s;
         }
         __syncthreads();
         // the next field's x-pass writes X only; Y is rewritten after the
         // next barrier, which every thread reaches after this z-pass
         for (int q = t; q < nz; q += 256) {
-            const int kx = q % m, cy = q / m;
+            const int kx = q % cx, cy = q / cx;
             double s = 0.0;
 #pragma unroll
-            for (int kz = 0; kz < np; ++kz) s += wz[kz] * Y[(kz * ny + cy) * m + kx];
-            img[(int64_t)f * sl.fstride + ((int64_t)sl.kz * m + (sl.y0 + cy)) * m + kx] = (T)s;
+            for (int kz = 0; kz < np; ++kz) s += wz[kz] * Y[(kz * ny + cy) * cx + kx];
+            img[(int64_t)f * sl.fstride + ((int64_t)sl.kz * m + (sl.y0 + cy)) * m + x0 + kx] = (T)s;
         }
     }
 }
 
 // copies into ghost cells and shadow boxes (sources: active cells, images)
 template <class T>
-__global__ __launch_bounds__(256) void k_xfer(const XlevelArgs a)
+__global__ __launch_bounds__(256) void k_xfer(const XlevelArgs a, int64_t nwork)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w = xcd_run(blockIdx.x, nwork);
+    const int64_t q = w * blockDim.x + threadIdx.x;
     if (q >= a.nxfer) return;
     const XferItem it = a.xfer[q];
     const T* __restrict__ src = (const T*)((it.kind & 1) ? a.image : a.reg) + it.src;
@@ -188,11 +193,13 @@ __global__ __launch_bounds__(256) void k_prolong(const XlevelArgs a)
 
 // grouped prolongation: one coarse parent, up to 8 fine children, separable
 // (x, then y, then z) over the union stencil; one thread per group and field
-// (grid y = field)
+// (work item = field-major (field, run of 256 groups))
 template <class T, int NP>
-__global__ __launch_bounds__(256) void k_prolong_group(const XlevelArgs a)
+__global__ __launch_bounds__(256) void k_prolong_group(const XlevelArgs a, int64_t ngx, int64_t nwork)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w = xcd_run(blockIdx.x, nwork);
+    if (w >= nwork) return;
+    const int64_t q = (w % ngx) * blockDim.x + threadIdx.x;
     if (q >= a.npgrp) return;
     const ProlongGroup it = a.pgrp[q];
     const BlockDev B = a.blocks[it.block];
@@ -205,7 +212,7 @@ __global__ __launch_bounds__(256) void k_prolong_group(const XlevelArgs a)
     const double* w0 = a.pw;           // parity 0 weights, union points 0..np-1
     const double* w1 = a.pw + 8;       // parity 1 weights, union points even..even+np-1
     {
-        const int f = blockIdx.y;
+        const int f = (int)(w / ngx);
         const T* p = sh + (int64_t)f * it.fstride;
         double acc[2][2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
 #pragma unroll 1
@@ -243,10 +250,11 @@ static void launch_xlevel_np(const XlevelArgs& a, hipStream_t s)
 {
     const unsigned gx = (unsigned)((a.nxfer + 255) / 256), gp = (unsigned)((a.nprol + 255) / 256);
     const unsigned gg = (unsigned)((a.npgrp + 255) / 256);
-    if (a.nislice) hipLaunchKernelGGL((k_restrict_image<T, NP>), dim3((unsigned)a.nislice), dim3(256), 0, s, a);
-    if (gx) hipLaunchKernelGGL(k_xfer<T>, dim3(gx), dim3(256), 0, s, a);
+    if (a.nislice) hipLaunchKernelGGL((k_restrict_image<T, NP>), dim3(xcd_grid(a.nislice)), dim3(256), 0, s, a);
+    if (gx) hipLaunchKernelGGL(k_xfer<T>, dim3(xcd_grid(gx)), dim3(256), 0, s, a, (int64_t)gx);
     if (gp) hipLaunchKernelGGL(k_prolong<T>, dim3(gp), dim3(256), 0, s, a);
-    if (gg) hipLaunchKernelGGL((k_prolong_group<T, NP>), dim3(gg, NF), dim3(256), 0, s, a);
+    if (gg) hipLaunchKernelGGL((k_prolong_group<T, NP>), dim3(xcd_grid((int64_t)gg * NF)), dim3(256), 0, s, a,
+                               (int64_t)gg, (int64_t)gg * NF);
 }
 
 template <class T>

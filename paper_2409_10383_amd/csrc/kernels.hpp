@@ -43,6 +43,18 @@ struct FillArgs {
 // the weight set d (evaluation point at the fine face o + d).  Centred where
 // it fits; for odd np the extra point goes towards the block's interior;
 // clamped to the block's active cells.
+// Workgroup slot -> work index for a 1-D launch of xcd_grid(nwork) slots:
+// slot b runs on XCD b % 8 (each XCD has its own L2), so that XCD receives
+// the contiguous run x*per .. x*per+per-1 of the work list and neighbouring
+// items, which read overlapping source lines, share one L2.  Indices >= nwork
+// are padding slots and do nothing.
+__device__ __forceinline__ int64_t xcd_run(int64_t slot, int64_t nwork)
+{
+    const int64_t per = (nwork + 7) / 8;
+    return (slot % 8) * per + slot / 8;
+}
+inline unsigned xcd_grid(int64_t nwork) { return (unsigned)((nwork + 7) / 8 * 8); }
+
 __device__ __forceinline__ void rwin(int kc, int n, int np, int& o, int& d)
 {
     const int c = 2 * kc;

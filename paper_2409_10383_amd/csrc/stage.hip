@@ -46,7 +46,7 @@ template <int N, int TX, int TY, int TZ> struct TileGeom {
 // buffers (the next field streams in while the current one is used) when
 // they fit in a CU's 160 KB, else one.
 template <class G, class C> struct StageLds {
-    static constexpr int REST = (G::NDX + G::NDY + NF * 256) * (int)sizeof(C);
+    static constexpr int REST = (G::NDX + G::NDY + NF * 256) * (int)sizeof(C) + 27 * 4;
     static constexpr int NBUF = (2 * G::NS * (int)sizeof(C) + REST <= 160 * 1024) ? 2 : 1;
 };
 
@@ -125,9 +125,9 @@ __device__ __forceinline__ int work_index(int slot, int nwork)
     return x * per + k;
 }
 
-template <int N, class T, class C, int TX, int TY, int TZ>
+template <int N, class T, class C, int TX, int TY, int TZ, bool W>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w, C* tile, C* dxs,
-                                           C* dys, C* adks);
+                                           C* dys, C* adks, int* vtab);
 
 // Waves per SIMD the compiler is asked to fit: FP32 storage fits two (the
 // 8th-order kernels would otherwise take 289 registers, one wave; asking for
@@ -140,7 +140,10 @@ template <class T> struct StageWaves {
 
 // One launch per stage.  With a.persistent the grid is sized to the
 // resident workgroups and each loops over its XCD's share of the work.
-template <int N, class T, class C, int TX, int TY, int TZ>
+// W: the staged tiles are copied in 16-byte pieces (FP32 storage always;
+// FP64 when the ghost depth and the halo differ by an even count, which the
+// launch checks), else FP64 fields go as 4-byte halves.
+template <int N, class T, class C, int TX, int TY, int TZ, bool W>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<T>::value))) void k_stage(
     const StageArgs a)
 {
@@ -149,9 +152,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<
     __shared__ C dxs[G::NDX];
     __shared__ C dys[G::NDY];
     __shared__ C adks[NF * 256];   // advection + dissipation, per field and zone
+    __shared__ int vtab[27];       // the tile's block: halo offsets per direction
     if (!a.persistent) {
         const int w = work_index(blockIdx.x, a.nwork);
-        if (w < a.nwork) stage_tile<N, T, C, TX, TY, TZ>(a, a.work[w], tile, dxs, dys, adks);
+        if (w < a.nwork) stage_tile<N, T, C, TX, TY, TZ, W>(a, a.work[w], tile, dxs, dys, adks, vtab);
         return;
     }
     // persistent: XCD x = blockIdx % 8 walks items x*per .. x*per+per-1
@@ -160,14 +164,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<
     for (int k = k0; k < per; k += nk) {
         const int w = x * per + k;
         if (w >= a.nwork) break;
-        stage_tile<N, T, C, TX, TY, TZ>(a, a.work[w], tile, dxs, dys, adks);
+        stage_tile<N, T, C, TX, TY, TZ, W>(a, a.work[w], tile, dxs, dys, adks, vtab);
         lds_barrier();
     }
 }
 
-template <int N, class T, class C, int TX, int TY, int TZ>
+template <int N, class T, class C, int TX, int TY, int TZ, bool W>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w, C* tile, C* dxs,
-                                           C* dys, C* adks)
+                                           C* dys, C* adks, int* vtab)
 {
     using G = TileGeom<N, TX, TY, TZ>;
     constexpr int R = G::R, SX = G::SX, SY = G::SY;
@@ -292,12 +296,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     constexpr int NRS = (NSLOT + 255) / 256;
     // 16-byte FP64 copies need a 16-byte aligned tile origin: E, every field
     // base and the tile's x origin are even when the ghost depth and the halo
-    // differ by an even count; otherwise FP64 fields go as 4-byte halves
-    const bool wide = sizeof(T) == 4 || ((g - R) & 1) == 0;
+    // differ by an even count (W); otherwise FP64 fields go as 4-byte halves
+    constexpr bool wide = W;
     // staged cells outside the block read a same-level neighbour directly
     // where the pack provides a virtual halo for that direction (the offset
     // table then points the block's ghosted index at the neighbour's cells)
-    const int64_t* vn = a.vnbr + (int64_t)w.block * 27;
+    // (one load per direction into LDS: the copy offsets below then read the
+    // table there instead of waiting on one global load per slot)
+    if (t < 27) vtab[t] = (int)(a.vnbr[(int64_t)w.block * 27 + t] - B.off);
+    lds_barrier();
     // clamped outflow directions read the block's own active cells, with the
     // y and z of the staged cell clamped to the active range
     const uint32_t cm = a.cmask[w.block];
@@ -312,7 +319,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
         const bool clamp = (cm >> dir) & 1u;
         const int cy = clamp ? (ly < 0 ? 0 : (ly >= n ? n - 1 : ly)) : ly;
         const int cz = clamp ? (lz < 0 ? 0 : (lz >= n ? n - 1 : lz)) : lz;
-        soff[r] = (int)(vn[dir] - B.off) + ((cz + g) * E + (cy + g)) * E + (lx + g);
+        soff[r] = vtab[dir] + ((cz + g) * E + (cy + g)) * E + (lx + g);
     }
     auto issue = [&](int f, C* buf) {
         if (wide) {
@@ -535,10 +542,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
 template <int N, int TX, int TY, int TZ>
 static hipError_t launch_v(int prec, const StageArgs& a, int grid, hipStream_t s)
 {
-    if (prec == 0)
-        hipLaunchKernelGGL((k_stage<N, double, double, TX, TY, TZ>), dim3(grid), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_stage<N, float, float, TX, TY, TZ>), dim3(grid), dim3(256), 0, s, a);
+    if (prec == 0) {
+        // 16-byte FP64 copies when the ghost depth and the halo N+1 differ by
+        // an even count
+        if (((a.g - (N + 1)) & 1) == 0)
+            hipLaunchKernelGGL((k_stage<N, double, double, TX, TY, TZ, true>), dim3(grid), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_stage<N, double, double, TX, TY, TZ, false>), dim3(grid), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_stage<N, float, float, TX, TY, TZ, true>), dim3(grid), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -566,13 +579,14 @@ hipError_t launch_stage(int N, int prec, int variant, const StageArgs& a, int gr
     return hipErrorInvalidValue;
 }
 
-// resident workgroups per CU of a variant (for the persistent grid)
+// resident workgroups per CU of a variant (for the persistent grid; the
+// FP64 kernels with 4-byte copies hold one workgroup per CU like the others)
 int stage_occupancy(int N, int prec, int variant)
 {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
 #define Z4C_OCC(NN, TT, X, Y, Z) \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stage<NN, TT, TT, X, Y, Z>, 256, 0)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stage<NN, TT, TT, X, Y, Z, true>, 256, 0)
 #define Z4C_OCCV(NN, TT)                                                     \
     switch (variant) {                                                        \
     case 0: Z4C_OCC(NN, TT, 8, 8, 4); break;                                  \
