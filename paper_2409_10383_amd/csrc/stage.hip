@@ -237,22 +237,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
         myz = fd1<N, C>(dys + own_y, TX * TY);
     };
 
-    // ---- centre values needed before the sweep: shift, conformal metric
+    // centre values needed by the sweep: shift, conformal metric and its
+    // inverse (loaded once the first field's copy is under way)
     C be[3], gdn[6], gu[6];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) be[q] = (C)srcb[(F_BETAX + q) * slab + cz];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) gdn[q] = (C)srcb[(F_GXX + q) * slab + cz];
-    {
-        const C c0 = gdn[3] * gdn[5] - gdn[4] * gdn[4];
-        const C c1 = gdn[2] * gdn[4] - gdn[1] * gdn[5];
-        const C c2 = gdn[1] * gdn[4] - gdn[2] * gdn[3];
-        const C id = (C)1 / (gdn[0] * c0 + gdn[1] * c1 + gdn[2] * c2);
-        gu[0] = c0 * id; gu[1] = c1 * id; gu[2] = c2 * id;
-        gu[3] = (gdn[0] * gdn[5] - gdn[2] * gdn[2]) * id;
-        gu[4] = (gdn[1] * gdn[2] - gdn[0] * gdn[4]) * id;
-        gu[5] = (gdn[0] * gdn[3] - gdn[1] * gdn[1]) * id;
-    }
     const bool adv = (P.terms & 4u) != 0;
     const bool adv_gauge = adv && (P.terms & 2u);
     const C sig = (P.terms & 8u) ? (C)P.ko_sigma : (C)0;
@@ -346,13 +333,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
         return sl < 6 ? F_GXX + sl : sl == 6 ? F_CHI : sl == 7 ? F_ALPHA : sl < 11 ? F_BETAX + (sl - 8)
              : sl < 14 ? F_GAMX + (sl - 11) : sl == 14 ? F_KH : sl == 15 ? F_TH : F_AXX + (sl - 16);
     };
-    issue(field_of(0), tile);
-#pragma unroll 1
-    for (int sl = 0; sl < NF; ++sl) {
-        cur = (NBUF == 2 && (sl & 1)) ? tile + G::NS : tile;
-        wait_vmem();
-        __syncthreads();   // field sl in LDS; every wave is done with field sl-1
-        if (NBUF == 2 && sl + 1 < NF) issue(field_of(sl + 1), (sl & 1) ? tile : tile + G::NS);
+    // processing of field slot sl, staged in LDS at cur
+    auto process = [&](int sl) __attribute__((always_inline)) {
         if (sl < 6) {
             // conformal metric: first derivatives, Ricci second-derivative term
             const int p = sl;
@@ -444,20 +426,55 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
             }
             put_adk(F_AXX + (sl - 16), ad * ih);
         }
-        if (NBUF == 1 && sl + 1 < NF) {
+    };
+    issue(field_of(0), tile);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) be[q] = (C)srcb[(F_BETAX + q) * slab + cz];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) gdn[q] = (C)srcb[(F_GXX + q) * slab + cz];
+    {
+        const C c0 = gdn[3] * gdn[5] - gdn[4] * gdn[4];
+        const C c1 = gdn[2] * gdn[4] - gdn[1] * gdn[5];
+        const C c2 = gdn[1] * gdn[4] - gdn[2] * gdn[3];
+        const C id = (C)1 / (gdn[0] * c0 + gdn[1] * c1 + gdn[2] * c2);
+        gu[0] = c0 * id; gu[1] = c1 * id; gu[2] = c2 * id;
+        gu[3] = (gdn[0] * gdn[5] - gdn[2] * gdn[2]) * id;
+        gu[4] = (gdn[1] * gdn[2] - gdn[0] * gdn[4]) * id;
+        gu[5] = (gdn[0] * gdn[3] - gdn[1] * gdn[1]) * id;
+    }
+#pragma unroll 1
+    for (int sl = 0; sl < NF - 1; ++sl) {
+        cur = (NBUF == 2 && (sl & 1)) ? tile + G::NS : tile;
+        wait_vmem();
+        __syncthreads();   // field sl in LDS; every wave is done with field sl-1
+        if (NBUF == 2) issue(field_of(sl + 1), (sl & 1) ? tile : tile + G::NS);
+        process(sl);
+        if (NBUF == 1) {
             lds_barrier();     // every wave is done with the single buffer
             issue(field_of(sl + 1), tile);
         }
     }
+    // the last field (a component of A~, light on registers), with the
+    // centre values of the per-zone algebra loaded at its start so that their
+    // latency overlaps it
+    C chi, Kh, Th, al, A[6], Gam[3];
+    {
+        constexpr int sl = NF - 1;
+        cur = (NBUF == 2 && (sl & 1)) ? tile + G::NS : tile;
+        wait_vmem();
+        __syncthreads();
+        chi = (C)srcb[F_CHI * slab + cz];
+        Kh = (C)srcb[F_KH * slab + cz];
+        Th = (C)srcb[F_TH * slab + cz];
+        al = (C)srcb[F_ALPHA * slab + cz];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) A[q] = (C)srcb[(F_AXX + q) * slab + cz];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) Gam[q] = (C)srcb[(F_GAMX + q) * slab + cz];
+        process(sl);
+    }
 
-    // ---- centre values and the per-zone algebra
-    const C chi = (C)srcb[F_CHI * slab + cz], Kh = (C)srcb[F_KH * slab + cz];
-    const C Th = (C)srcb[F_TH * slab + cz], al = (C)srcb[F_ALPHA * slab + cz];
-    C A[6], Gam[3];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) A[q] = (C)srcb[(F_AXX + q) * slab + cz];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) Gam[q] = (C)srcb[(F_GAMX + q) * slab + cz];
+    // ---- the per-zone algebra
 
     // RK inputs of this zone (U for stages 1-3, the accumulator for 2-4).
     // FP64: loaded before the algebra so that their latency overlaps it (the
