@@ -208,7 +208,12 @@ int z4c_rhs(struct z4c_pack *pack, int32_t src_reg, void *rhs_out, void *stream)
  * boundary condition is USER, preceded by the ghost fill of the stage input
  * (where a block's neighbour region in some direction is one block of the
  * same level and size, the stage reads that neighbour's active cells
- * directly and those ghost cells are not written; z4c_fill_ghosts always
+ * directly and those ghost cells are not written, except in directions with
+ * an x component for FP32 storage or an odd FP64 ghost depth: there the
+ * stage kernel writes such a neighbour's ghosts itself, into the register it
+ * writes, and the fill of stages 2-4 leaves them alone when the previous
+ * call of this function on the pack was the preceding stage, so the input
+ * register must then hold what that stage wrote; z4c_fill_ghosts always
  * writes every ghost cell):
  *   1: k1=F(U):  S1 = U + dt/2 k1, A  = U + dt/6 k1
  *   2: k2=F(S1): S2 = U + dt/2 k2, A += dt/3 k2

@@ -371,6 +371,10 @@ int build_xlevel(z4c_pack* pk)
                 pk->islice.push_back(sl);
             }
     }
+    // copies from active cells first: they need neither the restriction nor
+    // the same-level fill, and run beside them
+    std::stable_partition(pk->xfer.begin(), pk->xfer.end(), [](const XferItem& it) { return it.kind == 2; });
+    pk->nxfer_direct = std::count_if(pk->xfer.begin(), pk->xfer.end(), [](const XferItem& it) { return it.kind == 2; });
     return Z4C_OK;
 }
 
@@ -380,14 +384,20 @@ int build_xlevel(z4c_pack* pk)
 // stage path's ghost fill leaves those ghost cells alone.  vnbr[27 b + idx]
 // is the element offset that puts the ghosted index of block b's frame onto
 // the neighbour's cells (the block's own offset where the ghosts are real).
-// FP64 tiles are copied in 16-byte lanes (two cells of an x row, even in
-// the ghosted frame), which must stay within one block's memory.  With an
-// even ghost depth no lane crosses a block face, and every direction can be
-// virtual.  With an odd one the lanes at the x faces straddle them, so only
-// directions with dx = 0 are virtual and a lane takes its direction from its
-// y and z alone: across the x face it reads that neighbour's own x ghosts,
-// which stay real.  Lanes that are not 16-byte aligned at all (ghost depth
-// and halo of different parity) copy per half cell from the block itself.
+// A staged row that takes its x halo from the neighbours spans three
+// blocks' memory.  With 16-byte FP64 lanes and an even ghost depth that
+// costs little, and every direction is read in place (virt_x).  With FP32
+// storage it costs the stage kernel more (12 % on the 512-block pack) than
+// the ghosts would, and with an odd FP64 ghost depth the lanes at the x
+// faces straddle them: there only directions with dx = 0 are read in
+// place, and directions with dx != 0 whose neighbour is one block of the
+// same level and size are pushed instead (pmask): the stage kernel writes
+// each zone near an x face into the neighbours' ghosts as well, so the
+// stage path's fill leaves them alone from the second stage of a step on,
+// and a staged lane takes its direction from y and z alone (across the x
+// face it reads its own, or that neighbour's, x ghosts).  FP64 lanes that
+// are not 16-byte aligned (ghost depth and halo of different parity) copy
+// per half cell from the block itself: no direction is virtual or pushed.
 // Outflow boundaries: where every nonzero component of a direction with
 // dx = 0 leaves the domain, the outflow ghost is the block's own active cell
 // with y and z clamped to its active range (the block spans the domain edge),
@@ -399,13 +409,14 @@ void build_virtual_halos(z4c_pack* pk)
     pk->vnbr.assign((size_t)27 * nb, 0);
     pk->vmask.assign(nb, 0u);
     pk->cmask.assign(nb, 0u);
+    pk->pmask.assign(nb, 0u);
     pk->virt_x = 1;
     for (int b = 0; b < nb; ++b)
         for (int i = 0; i < 27; ++i) pk->vnbr[27 * b + i] = pk->bdev[b].off;
     const bool fp64 = pk->p.precision == Z4C_FP64;
     if (pk->p.bc == Z4C_BC_USER) return;
     if (fp64 && ((g - R) & 1)) return;
-    if (fp64 && (g & 1)) pk->virt_x = 0;
+    if (!fp64 || (g & 1)) pk->virt_x = 0;
     std::map<std::tuple<int, int, int64_t, int64_t, int64_t>, int> at;   // (level, n, ilo) -> block
     for (int b = 0; b < nb; ++b) {
         const z4c_block& B = pk->blk[b];
@@ -433,7 +444,6 @@ void build_virtual_halos(z4c_pack* pk)
                             continue;
                         }
                     }
-                    if (dx && !pk->virt_x) continue;
                     int64_t J[3];
                     bool inside = true;
                     for (int a = 0; a < 3; ++a) {
@@ -454,7 +464,8 @@ void build_virtual_halos(z4c_pack* pk)
                     if (std::llabs(v - D.off) > ((int64_t)1 << 30)) continue;
                     const int idx = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
                     pk->vnbr[27 * b + idx] = v;
-                    pk->vmask[b] |= 1u << idx;
+                    if (dx && !pk->virt_x) pk->pmask[b] |= 1u << idx;
+                    else pk->vmask[b] |= 1u << idx;
                 }
     }
 }
@@ -656,6 +667,7 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
     pk->ws_vnbr = o;   o = align256(o + sizeof(int64_t) * 27 * nblocks);
     pk->ws_vmask = o;  o = align256(o + sizeof(uint32_t) * nblocks);
     pk->ws_cmask = o;  o = align256(o + sizeof(uint32_t) * nblocks);
+    pk->ws_pmask = o;  o = align256(o + sizeof(uint32_t) * nblocks);
     pk->ws_track = o;  o = align256(o + sizeof(double) * 9 * Z4C_MAXTRACK);
     pk->ws_flag = o;   o = align256(o + sizeof(int32_t));
     pk->ws_total = o;
@@ -729,6 +741,9 @@ int z4c_pack_bind(z4c_pack* pk, void* const regs[Z4C_NREG], void* workspace, siz
     if (e == hipSuccess)
         e = hipMemcpyAsync(ws + pk->ws_cmask, pk->cmask.data(), sizeof(uint32_t) * pk->cmask.size(),
                            hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + pk->ws_pmask, pk->pmask.data(), sizeof(uint32_t) * pk->pmask.size(),
+                           hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !pk->islice.empty())
         e = hipMemcpyAsync(ws + pk->ws_islice, pk->islice.data(), sizeof(ImageSlice) * pk->islice.size(),
                            hipMemcpyHostToDevice, s);
@@ -761,6 +776,7 @@ int z4c_pack_bind(z4c_pack* pk, void* const regs[Z4C_NREG], void* workspace, siz
     for (int r = 0; r < Z4C_NREG; ++r) pk->reg[r] = regs[r];
     pk->ws = ws;
     pk->bound = true;
+    pk->last_stage = 0;
     pk->err.clear();
     return Z4C_OK;
 }
@@ -811,11 +827,14 @@ const char* z4c_last_error(const z4c_pack* pk) { return pk ? pk->err.c_str() : "
 
 // ghost fill; `virt` leaves the ghost cells of virtual-halo directions
 // (read directly from neighbours by the stage kernel) unwritten
-static int fill_impl(z4c_pack* pk, int32_t reg, void* stream, bool virt)
+// virt: leave the virtual (read in place) directions alone; pushed: also
+// those the previous stage kernel wrote into the register
+static int fill_impl(z4c_pack* pk, int32_t reg, void* stream, bool virt, bool pushed = false)
 {
     if (pk->p.bc == Z4C_BC_USER) return Z4C_OK;
     FillArgs a;
     a.skip = virt ? reinterpret_cast<const uint32_t*>(pk->ws + pk->ws_vmask) : nullptr;
+    a.skip2 = (virt && pushed) ? reinterpret_cast<const uint32_t*>(pk->ws + pk->ws_pmask) : nullptr;
     a.reg = pk->reg[reg];
     a.blocks = reinterpret_cast<const BlockDev*>(pk->ws + pk->ws_blocks);
     a.map = reinterpret_cast<const int32_t*>(pk->ws + pk->ws_map);
@@ -826,21 +845,17 @@ static int fill_impl(z4c_pack* pk, int32_t reg, void* stream, bool virt)
     a.maxghost = pk->maxghost;
     ProfScope ps(pk, as_stream(stream), 1);
     const hipStream_t s = as_stream(stream);
-    // the same-level copies and the cross-level chain (restriction, transfers,
-    // prolongation) read only active cells and write disjoint ghost cells, so
-    // on multi-level packs the former runs on the side stream beside the latter
+    // The same-level copies and the cross-level chain (restriction, copies
+    // into coarse ghosts and shadow boxes, prolongation) read only active
+    // cells, except the prolongation, which reads the shadow boxes, and they
+    // write disjoint cells.  On multi-level packs the side stream takes the
+    // same-level copies and the shadow-box copies from active cells, the
+    // stream itself the restriction and the copies from images; the
+    // prolongation waits for both.
     const bool fork = pk->multilevel && pk->side;
     hipError_t e = hipSuccess;
-    if (fork) {
-        e = hipEventRecord(pk->fork_ev, s);
-        if (e == hipSuccess) e = hipStreamWaitEvent(pk->side, pk->fork_ev, 0);
-        if (e == hipSuccess) e = launch_fill(pk->p.precision, a, (int)pk->blk.size(), pk->side);
-        if (e == hipSuccess) e = hipEventRecord(pk->join_ev, pk->side);
-    } else {
-        e = launch_fill(pk->p.precision, a, (int)pk->blk.size(), s);
-    }
-    if (e == hipSuccess && pk->multilevel) {
-        XlevelArgs x;
+    XlevelArgs x = {};
+    if (pk->multilevel) {
         x.reg = pk->reg[reg];
         x.shadow = pk->ws + pk->ws_shadow;
         x.image = pk->ws + pk->ws_image;
@@ -856,12 +871,32 @@ static int fill_impl(z4c_pack* pk, int32_t reg, void* stream, bool virt)
         x.pgrp = reinterpret_cast<const ProlongGroup*>(pk->ws + pk->ws_pgrp);
         x.npgrp = (int64_t)pk->pgrp.size();
         x.npts = pk->p.nghost + 1;
-        e = launch_xlevel(pk->p.precision, x, s);
     }
-    // join even after a failed launch, so that a capture on s stays closed
+    const XferItem* xf = x.xfer;
+    const int64_t nall = x.nxfer, ndir = pk->nxfer_direct;
     if (fork) {
+        e = hipEventRecord(pk->fork_ev, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(pk->side, pk->fork_ev, 0);
+        if (e == hipSuccess) e = launch_fill(pk->p.precision, a, (int)pk->blk.size(), pk->side);
+        if (e == hipSuccess) {
+            x.xfer = xf;
+            x.nxfer = ndir;
+            e = launch_xlevel(pk->p.precision, x, pk->side, XL_XFER);
+        }
+        if (e == hipSuccess) e = hipEventRecord(pk->join_ev, pk->side);
+        if (e == hipSuccess) {
+            x.xfer = xf + ndir;
+            x.nxfer = nall - ndir;
+            e = launch_xlevel(pk->p.precision, x, s, XL_RESTRICT | XL_XFER);
+        }
+        // join even after a failed launch, so that a capture on s stays closed
         const hipError_t j = hipStreamWaitEvent(s, pk->join_ev, 0);
         if (e == hipSuccess) e = j;
+        if (e == hipSuccess) e = launch_xlevel(pk->p.precision, x, s, XL_PROLONG);
+    } else {
+        e = launch_fill(pk->p.precision, a, (int)pk->blk.size(), s);
+        if (e == hipSuccess && pk->multilevel)
+            e = launch_xlevel(pk->p.precision, x, s, XL_RESTRICT | XL_XFER | XL_PROLONG);
     }
     if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "ghost fill launch: %s", hipGetErrorString(e));
     return Z4C_OK;
@@ -889,6 +924,7 @@ static StageArgs stage_args(z4c_pack* pk)
     a.U = pk->reg[Z4C_REG_U];
     a.vnbr = reinterpret_cast<const int64_t*>(pk->ws + pk->ws_vnbr);
     a.cmask = reinterpret_cast<const uint32_t*>(pk->ws + pk->ws_cmask);
+    a.pmask = reinterpret_cast<const uint32_t*>(pk->ws + pk->ws_pmask);
     a.virt_x = pk->virt_x;
     return a;
 }
@@ -917,7 +953,10 @@ int z4c_rk4_stage(z4c_pack* pk, int32_t stage, double dt, void* stream)
     if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
     static const int src_of[5] = {0, Z4C_REG_U, Z4C_REG_S1, Z4C_REG_S2, Z4C_REG_S1};
     static const int dst_of[5] = {0, Z4C_REG_S1, Z4C_REG_S2, Z4C_REG_S1, Z4C_REG_U};
-    int rc = fill_impl(pk, src_of[stage], stream, true);
+    // stages 2-4 read the register the previous stage wrote, x-face ghosts
+    // of same-level neighbours included, when that stage ran last
+    int rc = fill_impl(pk, src_of[stage], stream, true, stage >= 2 && pk->last_stage == stage - 1);
+    pk->last_stage = 0;
     if (rc) return rc;
     if (pk->ntrack > 0) {
         hipError_t te = track_stage(pk, stage, src_of[stage], dt, as_stream(stream));
@@ -932,6 +971,7 @@ int z4c_rk4_stage(z4c_pack* pk, int32_t stage, double dt, void* stream)
     const int grid = pk->persistent ? pk->grid_persistent : stage_grid(pk->work.size());
     hipError_t e = launch_stage(pk->p.fd_order / 2, pk->p.precision, pk->variant, a, grid, as_stream(stream));
     if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "stage launch: %s", hipGetErrorString(e));
+    pk->last_stage = stage;
     return Z4C_OK;
 }
 

@@ -60,7 +60,8 @@ __global__ __launch_bounds__(256) void k_fill_same(const FillArgs a)
     if (a.skip) {
         const int dx = i < g ? 0 : (i >= g + n ? 2 : 1), dy = j < g ? 0 : (j >= g + n ? 2 : 1),
                   dz = k < g ? 0 : (k >= g + n ? 2 : 1);
-        if ((a.skip[b] >> ((dz * 3 + dy) * 3 + dx)) & 1u) return;
+        const uint32_t sk = a.skip[b] | (a.skip2 ? a.skip2[b] : 0u);
+        if ((sk >> ((dz * 3 + dy) * 3 + dx)) & 1u) return;
     }
     int64_t G[3] = {(int64_t)B.ilo[0] + i - g, (int64_t)B.ilo[1] + j - g, (int64_t)B.ilo[2] + k - g};
 #pragma unroll
@@ -246,33 +247,35 @@ __global__ __launch_bounds__(256) void k_prolong_group(const XlevelArgs a, int64
 }
 
 template <class T, int NP>
-static void launch_xlevel_np(const XlevelArgs& a, hipStream_t s)
+static void launch_xlevel_np(const XlevelArgs& a, hipStream_t s, int ph)
 {
     const unsigned gx = (unsigned)((a.nxfer + 255) / 256), gp = (unsigned)((a.nprol + 255) / 256);
     const unsigned gg = (unsigned)((a.npgrp + 255) / 256);
-    if (a.nislice) hipLaunchKernelGGL((k_restrict_image<T, NP>), dim3(xcd_grid(a.nislice)), dim3(256), 0, s, a);
-    if (gx) hipLaunchKernelGGL(k_xfer<T>, dim3(xcd_grid(gx)), dim3(256), 0, s, a, (int64_t)gx);
-    if (gp) hipLaunchKernelGGL(k_prolong<T>, dim3(gp), dim3(256), 0, s, a);
-    if (gg) hipLaunchKernelGGL((k_prolong_group<T, NP>), dim3(xcd_grid((int64_t)gg * NF)), dim3(256), 0, s, a,
-                               (int64_t)gg, (int64_t)gg * NF);
+    if ((ph & XL_RESTRICT) && a.nislice)
+        hipLaunchKernelGGL((k_restrict_image<T, NP>), dim3(xcd_grid(a.nislice)), dim3(256), 0, s, a);
+    if ((ph & XL_XFER) && gx) hipLaunchKernelGGL(k_xfer<T>, dim3(xcd_grid(gx)), dim3(256), 0, s, a, (int64_t)gx);
+    if ((ph & XL_PROLONG) && gp) hipLaunchKernelGGL(k_prolong<T>, dim3(gp), dim3(256), 0, s, a);
+    if ((ph & XL_PROLONG) && gg)
+        hipLaunchKernelGGL((k_prolong_group<T, NP>), dim3(xcd_grid((int64_t)gg * NF)), dim3(256), 0, s, a,
+                           (int64_t)gg, (int64_t)gg * NF);
 }
 
 template <class T>
-static void launch_xlevel_t(const XlevelArgs& a, hipStream_t s)
+static void launch_xlevel_t(const XlevelArgs& a, hipStream_t s, int ph)
 {
     // stencil widths of the 4th/6th/8th-order ghost depths get unrolled kernels
     switch (a.npts) {
-    case 4: launch_xlevel_np<T, 4>(a, s); break;
-    case 5: launch_xlevel_np<T, 5>(a, s); break;
-    case 6: launch_xlevel_np<T, 6>(a, s); break;
-    default: launch_xlevel_np<T, 0>(a, s); break;
+    case 4: launch_xlevel_np<T, 4>(a, s, ph); break;
+    case 5: launch_xlevel_np<T, 5>(a, s, ph); break;
+    case 6: launch_xlevel_np<T, 6>(a, s, ph); break;
+    default: launch_xlevel_np<T, 0>(a, s, ph); break;
     }
 }
 
-hipError_t launch_xlevel(int prec, const XlevelArgs& a, hipStream_t s)
+hipError_t launch_xlevel(int prec, const XlevelArgs& a, hipStream_t s, int phases)
 {
-    if (prec == 0) launch_xlevel_t<double>(a, s);
-    else launch_xlevel_t<float>(a, s);
+    if (prec == 0) launch_xlevel_t<double>(a, s, phases);
+    else launch_xlevel_t<float>(a, s, phases);
     return hipGetLastError();
 }
 

@@ -15,13 +15,14 @@ struct StageArgs {
     const WorkItem* work;
     const int64_t* vnbr;      // per block, 27 direction offsets of the staged halo
     const uint32_t* cmask;    // per block, directions read clamped (outflow)
+    const uint32_t* pmask;    // per block, x directions pushed to a same-level neighbour
+    int32_t virt_x;           // 0: a staged cell's halo direction ignores x
     ParamsDev P;
     double dt;
     int32_t stage;            // 1..4, 0 = RHS only
     int32_t g;
     int32_t nwork;            // work items
     int32_t persistent;       // 1: grid smaller than nwork, workgroups loop
-    int32_t virt_x;           // 0: a staged cell's halo direction ignores x
 };
 
 constexpr int NVARIANT = 4;
@@ -36,6 +37,7 @@ struct FillArgs {
     int32_t nroot[3];
     int32_t maxghost;         // ghost cells of the largest block
     const uint32_t* skip;     // per block, directions left alone (virtual halos); null = none
+    const uint32_t* skip2;    // per block, further directions left alone (pushed); null = none
 };
 
 // Restriction window of coarse cell kc (0 <= kc < n/2) inside a fine block
@@ -172,7 +174,10 @@ int stage_occupancy(int N, int prec, int variant);
 hipError_t launch_fill(int prec, const FillArgs& a, int nblocks, hipStream_t s);
 hipError_t launch_diag(int N, int prec, const DiagArgs& a, int nwork, hipStream_t s);
 hipError_t launch_check_finite(int prec, const FiniteArgs& a, int nwork, hipStream_t s);
-hipError_t launch_xlevel(int prec, const XlevelArgs& a, hipStream_t s);
+// phases of the cross-level fill, in this order: restriction of the images,
+// copies a.xfer[0 .. a.nxfer), prolongation
+enum : int { XL_RESTRICT = 1, XL_XFER = 2, XL_PROLONG = 4 };
+hipError_t launch_xlevel(int prec, const XlevelArgs& a, hipStream_t s, int phases);
 hipError_t launch_regrid(int prec, const RegridArgs& a, int nblocks, int maxn, hipStream_t s);
 
 }  // namespace z4c

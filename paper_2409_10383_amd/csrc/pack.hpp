@@ -21,7 +21,8 @@ struct z4c_pack {
     LookupDev L;
     bool multilevel = false;
     // cross-level fill tables
-    std::vector<XferItem> xfer;
+    std::vector<XferItem> xfer;       // copies from active cells first, then from images
+    int64_t nxfer_direct = 0;         // of which from active cells
     std::vector<ProlongItem> prol;
     std::vector<ProlongGroup> pgrp;
     std::vector<ImageSlice> islice;
@@ -37,7 +38,10 @@ struct z4c_pack {
     std::vector<uint32_t> vmask;  // directions the stage path's fill skips, per block
     std::vector<uint32_t> cmask;  // of those, the clamped outflow directions
     size_t ws_cmask = 0;
-    int virt_x = 1;               // 0: only directions with dx = 0 are virtual
+    int virt_x = 1;               // 1: directions with dx != 0 are read in place too
+    std::vector<uint32_t> pmask;  // per block, x directions whose ghosts the stage kernel pushes
+    size_t ws_pmask = 0;
+    int last_stage = 0;           // last RK stage run on the pack (0: none, or other work since)
     // puncture tracker: device state (x, k_prev, acc) per puncture in the workspace
     int ntrack = 0;
     size_t ws_track = 0;

@@ -258,6 +258,7 @@ int z4c_regrid_transfer(z4c_pack* src, int32_t src_reg, z4c_pack* dst, int32_t d
                 a.bc == b.bc && a.dx0 == b.dx0;
     for (int d = 0; d < 3; ++d) same = same && a.nroot[d] == b.nroot[d] && a.lo[d] == b.lo[d];
     if (!same) return fail(dst, Z4C_EINVAL, "regrid: packs describe different meshes or methods");
+    dst->last_stage = 0;   // a register of dst is rewritten
     // per destination block: where its data comes from
     std::map<std::tuple<int, int, int, int, int>, int> at;
     for (size_t s = 0; s < src->blk.size(); ++s) {

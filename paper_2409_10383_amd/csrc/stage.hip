@@ -287,7 +287,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     constexpr bool wide = W;
     // staged cells outside the block read a same-level neighbour directly
     // where the pack provides a virtual halo for that direction (the offset
-    // table then points the block's ghosted index at the neighbour's cells)
+    // table then points the block's ghosted index at the neighbour's cells);
+    // in pushed x directions the table gives the neighbour the zones near a
+    // face write their state to
     // (one load per direction into LDS: the copy offsets below then read the
     // table there instead of waiting on one global load per slot)
     if (t < 27) vtab[t] = (int)(a.vnbr[(int64_t)w.block * 27 + t] - B.off);
@@ -301,6 +303,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
         const int q = (r * 256 + t) * (SLOT / (int)sizeof(T));   // first element of the slot
         const int x = q % SX, y = (q / SX) % SY, z = q / sxy;
         const int lx = x + w.i0 - R, ly = y + w.j0 - R, lz = z + w.k0 - R;
+        // without virtual x directions the x halo is read from the block's
+        // own ghosts (same-level neighbours push them), so that a staged row
+        // stays one block's memory
         const int dir = ((lz < 0 ? 0 : (lz >= n ? 2 : 1)) * 3 + (ly < 0 ? 0 : (ly >= n ? 2 : 1))) * 3 +
                         (a.virt_x ? (lx < 0 ? 0 : (lx >= n ? 2 : 1)) : 1);
         const bool clamp = (cm >> dir) & 1u;
@@ -554,6 +559,26 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     T* __restrict__ dst = (T*)a.dst + B.off + cz;
 #pragma unroll
     for (int f = 0; f < NF; ++f) dst[f * slab] = (T)out[f];
+    // A zone within g of an x face is a ghost of the same-level neighbour
+    // across that face, and of the diagonal neighbours across it and a y or
+    // z face the zone is also near (a zone may be near both faces of an axis
+    // when n < 2g): the written state goes there too, so that the next
+    // stage finds those ghosts filled (the pack's fill leaves them alone)
+    // and stages every row from one block.
+    const uint32_t pm = a.pmask[w.block];
+    const int sxm = (i < g ? 1 : 0) | (i >= n - g ? 4 : 0);   // bit s: near the face of side s
+    if (pm && sxm) {
+        const int sym = 2 | (j < g ? 1 : 0) | (j >= n - g ? 4 : 0);
+        const int szm = 2 | (k < g ? 1 : 0) | (k >= n - g ? 4 : 0);
+#pragma unroll 1
+        for (int d = 0; d < 27; ++d) {
+            const int sx = d % 3, sy = (d / 3) % 3, sz = d / 9;
+            if (!((pm >> d) & 1u) || !((sxm >> sx) & 1) || !((sym >> sy) & 1) || !((szm >> sz) & 1)) continue;
+            T* __restrict__ gh = (T*)a.dst + B.off + vtab[d] + cz;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) gh[f * slab] = (T)out[f];
+        }
+    }
 }
 
 template <int N, int TX, int TY, int TZ>
