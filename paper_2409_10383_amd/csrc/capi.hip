@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -335,41 +336,54 @@ int build_xlevel(z4c_pack* pk)
                     }
                 }
     }
-    // image restriction work: per source block, coarse z-slices split into
-    // row chunks that fit the LDS budget; only chunks holding rows that a
-    // transfer reads are computed, each trimmed to its first and last such row
+    // image restriction work: per source block, runs of consecutive coarse
+    // z-planes that need the same rows (first to last row some transfer
+    // reads) and columns, split into row chunks that fit the LDS budget; a
+    // workgroup marches along its run keeping the y-passes of the last np
+    // fine planes, so that it reads each fine plane once
     for (int F = 0; F < nb; ++F) {
         if (pk->img_off[F] < 0) continue;
         const int m = pk->blk[F].n / 2;
         if (pk->blk[F].ilo[0] % 2 || pk->blk[F].ilo[1] % 2 || pk->blk[F].ilo[2] % 2) return Z4C_EINVAL;
         if (pk->blk[F].n < np) return Z4C_EUNSUPPORTED;
-        int cy = m;
-        while (cy > 1 && ((int64_t)m * (2 * cy + np) * np > RI_XMAX || (int64_t)m * cy * np > RI_YMAX)) cy /= 2;
-        if ((int64_t)m * (2 * cy + np) * np > RI_XMAX || (int64_t)m * cy * np > RI_YMAX) return Z4C_EUNSUPPORTED;
         const std::vector<uint8_t>& need = img_rows[F];
+        // per coarse plane: first and last needed row, first and last column
+        std::vector<std::array<int, 4>> pl((size_t)m, std::array<int, 4>{-1, -1, m, -1});
         for (int kz = 0; kz < m; ++kz)
-            for (int y0 = 0; y0 < m; y0 += cy) {
-                int lo = -1, hi = -1, xlo = m, xhi = -1;
-                for (int y = y0; y < std::min(y0 + cy, m); ++y)
-                    if (need[(size_t)kz * m + y]) {
-                        if (lo < 0) lo = y;
-                        hi = y;
-                        xlo = std::min<int>(xlo, img_xlo[F][(size_t)kz * m + y]);
-                        xhi = std::max<int>(xhi, img_xhi[F][(size_t)kz * m + y]);
-                    }
-                if (lo < 0) continue;
+            for (int y = 0; y < m; ++y)
+                if (need[(size_t)kz * m + y]) {
+                    std::array<int, 4>& q = pl[(size_t)kz];
+                    if (q[0] < 0) q[0] = y;
+                    q[1] = y;
+                    q[2] = std::min<int>(q[2], img_xlo[F][(size_t)kz * m + y]);
+                    q[3] = std::max<int>(q[3], img_xhi[F][(size_t)kz * m + y]);
+                }
+        for (int kz = 0; kz < m;) {
+            const std::array<int, 4> q = pl[(size_t)kz];
+            if (q[0] < 0) { ++kz; continue; }
+            int k1 = kz + 1;
+            while (k1 < m && pl[(size_t)k1] == q) ++k1;
+            const int cx = q[3] - q[2] + 1;
+            int cy = q[1] - q[0] + 1;
+            while (cy > 1 && ((int64_t)(2 * cy + np) * cx > RI_XMAX || (int64_t)np * cy * cx > RI_YMAX))
+                cy = (cy + 1) / 2;
+            if ((int64_t)(2 * cy + np) * cx > RI_XMAX || (int64_t)np * cy * cx > RI_YMAX) return Z4C_EUNSUPPORTED;
+            for (int y0 = q[0]; y0 <= q[1]; y0 += cy) {
                 ImageSlice sl;
                 std::memset(&sl, 0, sizeof(sl));
                 sl.img = pk->img_off[F];
                 sl.block = F;
                 sl.fstride = pk->img_fstride[F];
                 sl.kz = (int16_t)kz;
-                sl.y0 = (int16_t)lo;
-                sl.ny = (int16_t)(hi - lo + 1);
-                sl.x0 = (int16_t)xlo;
-                sl.nx = (int16_t)(xhi - xlo + 1);
+                sl.nkz = (int16_t)(k1 - kz);
+                sl.y0 = (int16_t)y0;
+                sl.ny = (int16_t)std::min(cy, q[1] - y0 + 1);
+                sl.x0 = (int16_t)q[2];
+                sl.nx = (int16_t)cx;
                 pk->islice.push_back(sl);
             }
+            kz = k1;
+        }
     }
     // copies from active cells first: they need neither the restriction nor
     // the same-level fill, and run beside them

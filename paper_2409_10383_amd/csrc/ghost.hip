@@ -86,62 +86,77 @@ __global__ __launch_bounds__(256) void k_fill_same(const FillArgs a)
 }
 
 // Coarse image of a fine block: separable x, y, z passes through LDS (the
-// same association order as a direct triple sum: x innermost).
+// same association order as a direct triple sum: x innermost).  A workgroup
+// takes one field of a run of coarse z-planes and marches along it: each
+// fine plane a window needs is read once, restricted in x and then in y
+// into a ring of the last np planes' y-passes (several new planes per pass
+// as the x-pass buffer allows), and every coarse plane is the z-pass over
+// its window's np ring entries.  Windows (clamped to the block, as the
+// restriction reads only the block's own cells) never move back, so the
+// ring holds them.
 template <class T, int NP>
 __global__ __launch_bounds__(256) void k_restrict_image(const XlevelArgs a)
 {
-    __shared__ double X[RI_XMAX];
-    __shared__ double Y[RI_YMAX];
-    const int64_t w = xcd_run(blockIdx.x, a.nislice);
-    if (w >= a.nislice) return;
-    const ImageSlice sl = a.islice[w];
+    __shared__ double X[RI_XMAX];    // x-passes of new fine planes: plane, row, column
+    __shared__ double Y[RI_YMAX];    // y-passes of the last np fine planes
+    const int64_t wi = xcd_run(blockIdx.x, a.nislice * NF);
+    if (wi >= a.nislice * NF) return;
+    const ImageSlice sl = a.islice[wi / NF];
+    const int f = (int)(wi % NF);
     const BlockDev F = a.blocks[sl.block];
     const int n = F.n, m = n >> 1, np = NP ? NP : a.npts, E = F.E, g = (E - n) >> 1;
-    const int t = threadIdx.x, ny = sl.ny;
-    int oz, dz, oy0, dy0, oy1, dy1;
-    rwin(sl.kz, n, np, oz, dz);
+    const int t = threadIdx.x, ny = sl.ny, x0 = sl.x0, cx = sl.nx;
+    int oy0, dy0, oy1, dy1;
     rwin(sl.y0, n, np, oy0, dy0);
     rwin(sl.y0 + ny - 1, n, np, oy1, dy1);
-    const int R = oy1 + np - oy0;    // fine rows staged per plane
-    const T* base = (const T*)a.reg + F.off + ((int64_t)(oz + g) * E + (oy0 + g)) * E + g;
-    T* img = (T*)a.image + sl.img;
-    const double* wz = a.rw + 8 * dz;
-    // coarse columns x0 .. x0 + cx - 1 only (those some transfer reads)
-    const int x0 = sl.x0, cx = sl.nx;
-    const int nxq = cx * R * np, nyq = cx * ny * np, nz = cx * ny;
-    for (int f = 0; f < NF; ++f) {
-        const T* p = base + (int64_t)f * F.slab;
-        for (int q = t; q < nxq; q += 256) {
-            const int kx = q % cx, r = (q / cx) % R, pz = q / (cx * R);
-            int ox, dx;
-            rwin(x0 + kx, n, np, ox, dx);
-            const T* row = p + ((int64_t)pz * E + r) * E + ox;
-            const double* wx = a.rw + 8 * dx;
-            double s = 0.0;
+    const int R = oy1 + np - oy0;    // fine rows read per plane
+    const int nxq = cx * R, nyq = cx * ny;
+    const int pmax = RI_XMAX / nxq;  // new planes per x-pass (the pack checks >= 1)
+    T* img = (T*)a.image + sl.img + (int64_t)f * sl.fstride;
+    // fine plane 0, row oy0, column 0 of field f
+    const T* p = (const T*)a.reg + F.off + (int64_t)f * F.slab + ((int64_t)g * E + (oy0 + g)) * E + g;
+    int hi = 0;                      // fine planes below hi are in the ring
+    for (int kz = sl.kz; kz < sl.kz + sl.nkz; ++kz) {
+        int oz, dz;
+        rwin(kz, n, np, oz, dz);
+        if (kz == sl.kz) hi = oz;
+        while (hi < oz + np) {
+            const int nnew = min(oz + np - hi, pmax);
+            for (int q = t; q < nnew * nxq; q += 256) {
+                const int pl = q / nxq, u = q - pl * nxq, kx = u % cx, r = u / cx;
+                int ox, dx;
+                rwin(x0 + kx, n, np, ox, dx);
+                const T* row = p + ((int64_t)(hi + pl) * E + r) * E + ox;
+                const double* wx = a.rw + 8 * dx;
+                double s = 0.0;
 #pragma unroll
-            for (int ix = 0; ix < np; ++ix) s += wx[ix] * (double)row[ix];
-            X[q] = s;
+                for (int ix = 0; ix < np; ++ix) s += wx[ix] * (double)row[ix];
+                X[q] = s;
+            }
+            // also orders the previous z-pass's ring reads before the
+            // y-pass below overwrites entries
+            __syncthreads();
+            for (int q = t; q < nnew * nyq; q += 256) {
+                const int pl = q / nyq, u = q - pl * nyq, kx = u % cx, cy = u / cx;
+                int oy, dy;
+                rwin(sl.y0 + cy, n, np, oy, dy);
+                const double* wy = a.rw + 8 * dy;
+                const double* Xp = X + pl * nxq;
+                double s = 0.0;
+#pragma unroll
+                for (int jy = 0; jy < np; ++jy) s += wy[jy] * Xp[(oy - oy0 + jy) * cx + kx];
+                Y[((hi + pl) % np) * nyq + u] = s;
+            }
+            __syncthreads();
+            hi += nnew;
         }
-        __syncthreads();
+        const double* wz = a.rw + 8 * dz;
         for (int q = t; q < nyq; q += 256) {
-            const int kx = q % cx, cy = (q / cx) % ny, pz = q / (cx * ny);
-            int oy, dy;
-            rwin(sl.y0 + cy, n, np, oy, dy);
-            const double* wy = a.rw + 8 * dy;
-            double s = 0.0;
-#pragma unroll
-            for (int jy = 0; jy < np; ++jy) s += wy[jy] * X[(pz * R + (oy - oy0 + jy)) * cx + kx];
-            Y[q] = s;
-        }
-        __syncthreads();
-        // the next field's x-pass writes X only; Y is rewritten after the
-        // next barrier, which every thread reaches after this z-pass
-        for (int q = t; q < nz; q += 256) {
             const int kx = q % cx, cy = q / cx;
             double s = 0.0;
 #pragma unroll
-            for (int kz = 0; kz < np; ++kz) s += wz[kz] * Y[(kz * ny + cy) * cx + kx];
-            img[(int64_t)f * sl.fstride + ((int64_t)sl.kz * m + (sl.y0 + cy)) * m + x0 + kx] = (T)s;
+            for (int kk = 0; kk < np; ++kk) s += wz[kk] * Y[((oz + kk) % np) * nyq + q];
+            img[((int64_t)kz * m + (sl.y0 + cy)) * m + x0 + kx] = (T)s;
         }
     }
 }
@@ -252,7 +267,7 @@ static void launch_xlevel_np(const XlevelArgs& a, hipStream_t s, int ph)
     const unsigned gx = (unsigned)((a.nxfer + 255) / 256), gp = (unsigned)((a.nprol + 255) / 256);
     const unsigned gg = (unsigned)((a.npgrp + 255) / 256);
     if ((ph & XL_RESTRICT) && a.nislice)
-        hipLaunchKernelGGL((k_restrict_image<T, NP>), dim3(xcd_grid(a.nislice)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_restrict_image<T, NP>), dim3(xcd_grid(a.nislice * NF)), dim3(256), 0, s, a);
     if ((ph & XL_XFER) && gx) hipLaunchKernelGGL(k_xfer<T>, dim3(xcd_grid(gx)), dim3(256), 0, s, a, (int64_t)gx);
     if ((ph & XL_PROLONG) && gp) hipLaunchKernelGGL(k_prolong<T>, dim3(gp), dim3(256), 0, s, a);
     if ((ph & XL_PROLONG) && gg)

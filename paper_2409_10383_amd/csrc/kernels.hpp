@@ -68,7 +68,7 @@ __device__ __forceinline__ void rwin(int kc, int n, int np, int& o, int& d)
 }
 
 // LDS budget of the image restriction (doubles): x-pass and y-pass partials
-constexpr int RI_XMAX = 4096, RI_YMAX = 1536;
+constexpr int RI_XMAX = 2048, RI_YMAX = 1536;
 
 struct XlevelArgs {
     void* reg;                // register being filled

@@ -60,12 +60,12 @@ struct XferItem {
     int32_t pad;
 };
 // One workgroup of the image restriction: coarse cells x0 .. x0+nx-1 of
-// rows y0 .. y0+ny-1 of coarse z-slice kz of block `block`.
+// rows y0 .. y0+ny-1 of the coarse z-planes kz .. kz+nkz-1 of block `block`.
 struct ImageSlice {
     int64_t img;          // element offset of the block's image (field 0)
     int32_t block;
     int32_t fstride;      // field stride of the image (elements)
-    int16_t kz, y0, ny, x0, nx, pad[3];
+    int16_t kz, nkz, y0, ny, x0, nx, pad[2];
 };
 // A prolongation fills one fine ghost cell from the (g+1)^3 coarse values
 // of its block's shadow box.
