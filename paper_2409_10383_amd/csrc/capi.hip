@@ -177,6 +177,7 @@ int build_xlevel(z4c_pack* pk)
     const int64_t per256 = 256 / (int64_t)esz;
     const int nb = (int)pk->blk.size();
     pk->img_off.assign(nb, -1);
+    std::vector<ProlongGroup> quads, pairs, singles;   // grouped prolongations
     // image rows (z-plane * m + y) some transfer reads, per source block
     // and the range of coarse x each such row needs
     std::vector<std::vector<uint8_t>> img_rows(nb);
@@ -218,6 +219,8 @@ int build_xlevel(z4c_pack* pk)
         int64_t shoff = -1;
         std::vector<uint8_t> mark;
         std::unordered_map<int64_t, size_t> pgmap;  // parent's child-(0,0,0) cell -> group
+        std::vector<ProlongGroup> bg;                // this block's groups
+        std::vector<int64_t> bkey;                   // and their keys
         for (int k = 0; k < E; ++k)
             for (int j = 0; j < E; ++j)
                 for (int i = 0; i < E; ++i) {
@@ -320,10 +323,11 @@ int build_xlevel(z4c_pack* pk)
                             pg.se = (int32_t)SE;
                             pg.mask = 0;
                             pg.fstride = (int32_t)fstride;
-                            itg = pgmap.emplace(key, pk->pgrp.size()).first;
-                            pk->pgrp.push_back(pg);
+                            itg = pgmap.emplace(key, bg.size()).first;
+                            bg.push_back(pg);
+                            bkey.push_back(key);
                         }
-                        pk->pgrp[itg->second].mask |= 1 << (cz * 4 + cy * 2 + cx);
+                        bg[itg->second].mask |= 1 << (cz * 4 + cy * 2 + cx);
                     } else {
                         ProlongItem pi;
                         pi.dst = dcell;
@@ -335,7 +339,46 @@ int build_xlevel(z4c_pack* pk)
                         pk->prol.push_back(pi);
                     }
                 }
+        // neighbouring parents along y and z (child-(0,0,0) keys two rows or
+        // two planes apart) are taken together, four (y and z) or two (y) at
+        // a time: one thread reads the union of their stencils (one more row,
+        // or row and plane), while neighbouring threads keep taking
+        // neighbouring parents along x, so a load still touches the lines of
+        // one row
+        const int64_t dy = 2 * (int64_t)(E + 2), dz = dy * (E + 2);
+        std::vector<uint8_t> used(bg.size(), 0);
+        auto partner = [&](size_t q, int64_t dk) -> int64_t {
+            const auto it2 = pgmap.find(bkey[q] + dk);
+            return (it2 == pgmap.end() || used[it2->second]) ? -1 : (int64_t)it2->second;
+        };
+        // (fours only for FP64: with 4-byte loads the wider thread costs more
+        // than the shared rows save)
+        for (size_t q = 0; q < bg.size() && pk->p.precision == Z4C_FP64; ++q) {
+            if (used[q]) continue;
+            const int64_t b1 = partner(q, dy), c1 = partner(q, dz), d1 = partner(q, dy + dz);
+            if (b1 < 0 || c1 < 0 || d1 < 0) continue;
+            ProlongGroup pg = bg[q];
+            pg.mask |= (bg[b1].mask << 8) | (bg[c1].mask << 16) | (bg[d1].mask << 24);
+            quads.push_back(pg);
+            used[q] = used[b1] = used[c1] = used[d1] = 1;
+        }
+        for (size_t q = 0; q < bg.size(); ++q) {
+            if (used[q]) continue;
+            const int64_t o1 = partner(q, dy);
+            if (o1 < 0) continue;
+            ProlongGroup pg = bg[q];
+            pg.mask |= bg[o1].mask << 8;
+            pairs.push_back(pg);
+            used[q] = used[o1] = 1;
+        }
+        for (size_t q = 0; q < bg.size(); ++q)
+            if (!used[q]) singles.push_back(bg[q]);
+        pk->nparent += (int64_t)bg.size();
     }
+    // by kind, so that few waves mix them
+    pk->pgrp = quads;
+    pk->pgrp.insert(pk->pgrp.end(), pairs.begin(), pairs.end());
+    pk->pgrp.insert(pk->pgrp.end(), singles.begin(), singles.end());
     // image restriction work: per source block, runs of consecutive coarse
     // z-planes that need the same rows (first to last row some transfer
     // reads) and columns, split into row chunks that fit the LDS budget; a
@@ -704,7 +747,7 @@ int z4c_pack_query(const z4c_pack* pk, z4c_layout* out)
     out->state_elem_bytes = pk->p.precision == Z4C_FP64 ? 8 : 4;
     out->nwork = (int32_t)pk->work.size();
     out->nxfer = (int64_t)pk->xfer.size();
-    out->nprolong = (int64_t)pk->prol.size() + 8 * (int64_t)pk->pgrp.size();
+    out->nprolong = (int64_t)pk->prol.size() + 8 * pk->nparent;
     return Z4C_OK;
 }
 

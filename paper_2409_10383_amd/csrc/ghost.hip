@@ -208,8 +208,12 @@ __global__ __launch_bounds__(256) void k_prolong(const XlevelArgs a)
 }
 
 // grouped prolongation: one coarse parent, up to 8 fine children, separable
-// (x, then y, then z) over the union stencil; one thread per group and field
-// (work item = field-major (field, run of 256 groups))
+// (x, then y, then z) over the union stencil; one thread per group and field.
+// A group may also hold the parent one coarse cell further in y (mask byte
+// 1), or those further in y, in z and in both (bytes 1-3): their stencils
+// are the first one's shifted by a row, a plane or both, so the thread reads
+// the union once (one more row, or row and plane) and every parent's sums
+// run in the same order as on its own.
 template <class T, int NP>
 __global__ __launch_bounds__(256) void k_prolong_group(const XlevelArgs a, int64_t ngx, int64_t nwork)
 {
@@ -227,37 +231,102 @@ __global__ __launch_bounds__(256) void k_prolong_group(const XlevelArgs a, int64
     const int64_t se = it.se, E = B.E;
     const double* w0 = a.pw;           // parity 0 weights, union points 0..np-1
     const double* w1 = a.pw + 8;       // parity 1 weights, union points even..even+np-1
-    {
-        const int f = (int)(w / ngx);
-        const T* p = sh + (int64_t)f * it.fstride;
-        double acc[2][2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
-#pragma unroll 1
-        for (int kz = 0; kz < nu; ++kz) {
-            double ay[2][2] = {{0, 0}, {0, 0}};
+    const uint32_t mask = (uint32_t)it.mask;
+    const int f = (int)(w / ngx);
+    const T* p = sh + (int64_t)f * it.fstride;
+    // x-pass of one union row
+    auto xpass = [&](const T* row, double& ax0, double& ax1) {
+        ax0 = 0.0;
+        ax1 = 0.0;
 #pragma unroll
-            for (int jy = 0; jy < nu; ++jy) {
-                const T* row = p + (kz * se + jy) * se;
-                double ax0 = 0.0, ax1 = 0.0;
-#pragma unroll
-                for (int ix = 0; ix < nu; ++ix) {
-                    const double v = (double)row[ix];
-                    if (ix < np) ax0 += w0[ix] * v;
-                    if (ix >= even) ax1 += w1[ix - even] * v;
-                }
-                if (jy < np) { ay[0][0] += w0[jy] * ax0; ay[0][1] += w0[jy] * ax1; }
-                if (jy >= even) { ay[1][0] += w1[jy - even] * ax0; ay[1][1] += w1[jy - even] * ax1; }
-            }
-            for (int cy = 0; cy < 2; ++cy)
-                for (int cx = 0; cx < 2; ++cx) {
-                    if (kz < np) acc[0][cy][cx] += w0[kz] * ay[cy][cx];
-                    if (kz >= even) acc[1][cy][cx] += w1[kz - even] * ay[cy][cx];
-                }
+        for (int ix = 0; ix < (NP ? NP + 1 : 9); ++ix) {
+            if (ix >= nu) continue;
+            const double v = (double)row[ix];
+            if (ix < np) ax0 += w0[ix] * v;
+            if (ix >= even) ax1 += w1[ix - even] * v;
         }
+    };
+    // y-pass term of union row jj of a parent's stencil
+    auto yterm = [&](int jj, double ax0, double ax1, double (&ay)[2][2]) {
+        if (jj < 0 || jj >= nu) return;
+        if (jj < np) { ay[0][0] += w0[jj] * ax0; ay[0][1] += w0[jj] * ax1; }
+        if (jj >= even) { ay[1][0] += w1[jj - even] * ax0; ay[1][1] += w1[jj - even] * ax1; }
+    };
+    // z-pass term of union plane kk of a parent's stencil
+    auto zterm = [&](int kk, const double (&ay)[2][2], double (&ac)[2][2][2]) {
+        if (kk < 0 || kk >= nu) return;
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                if (kk < np) ac[0][cy][cx] += w0[kk] * ay[cy][cx];
+                if (kk >= even) ac[1][cy][cx] += w1[kk - even] * ay[cy][cx];
+            }
+    };
+    // children of parent pb (0: this one, 1: +y, 2: +z, 3: +y+z)
+    auto store = [&](int pb, const double (&ac)[2][2][2]) {
         for (int cz = 0; cz < 2; ++cz)
             for (int cy = 0; cy < 2; ++cy)
                 for (int cx = 0; cx < 2; ++cx)
-                    if (it.mask & (1 << (cz * 4 + cy * 2 + cx)))
-                        dst[(cz * E + cy) * E + cx + (int64_t)f * B.slab] = (T)acc[cz][cy][cx];
+                    if (mask & (1u << (8 * pb + cz * 4 + cy * 2 + cx)))
+                        dst[((cz + 2 * (pb >> 1)) * E + cy + 2 * (pb & 1)) * E + cx + (int64_t)f * B.slab] =
+                            (T)ac[cz][cy][cx];
+    };
+    if constexpr (sizeof(T) == 8) if (mask >> 16) {
+        // four parents (FP64 packs only): nu + 1 planes of nu + 1 rows
+        double acc[4][2][2][2] = {};
+#pragma unroll 1
+        for (int kz = 0; kz <= nu; ++kz) {
+            double ay[2][2][2] = {};   // [row shift][cy][cx]
+#pragma unroll
+            for (int jy = 0; jy < (NP ? NP + 2 : 10); ++jy) {
+                if (jy > nu) continue;
+                double ax0, ax1;
+                xpass(p + (kz * se + jy) * se, ax0, ax1);
+                yterm(jy, ax0, ax1, ay[0]);
+                yterm(jy - 1, ax0, ax1, ay[1]);
+            }
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) zterm(kz - (pb >> 1), ay[pb & 1], acc[pb]);
+        }
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) store(pb, acc[pb]);
+        return;
+    }
+    if (mask >> 8) {
+        // two parents along y: nu planes of nu + 1 rows
+        double acc[2][2][2][2] = {};
+#pragma unroll 1
+        for (int kz = 0; kz < nu; ++kz) {
+            double ay[2][2][2] = {};
+#pragma unroll
+            for (int jy = 0; jy < (NP ? NP + 2 : 10); ++jy) {
+                if (jy > nu) continue;
+                double ax0, ax1;
+                xpass(p + (kz * se + jy) * se, ax0, ax1);
+                yterm(jy, ax0, ax1, ay[0]);
+                yterm(jy - 1, ax0, ax1, ay[1]);
+            }
+            zterm(kz, ay[0], acc[0]);
+            zterm(kz, ay[1], acc[1]);
+        }
+        store(0, acc[0]);
+        store(1, acc[1]);
+    } else {
+        double acc[2][2][2] = {};
+#pragma unroll 1
+        for (int kz = 0; kz < nu; ++kz) {
+            double ay[2][2] = {};
+#pragma unroll
+            for (int jy = 0; jy < (NP ? NP + 1 : 9); ++jy) {
+                if (jy >= nu) continue;
+                double ax0, ax1;
+                xpass(p + (kz * se + jy) * se, ax0, ax1);
+                yterm(jy, ax0, ax1, ay);
+            }
+            zterm(kz, ay, acc);
+        }
+        store(0, acc);
     }
 }
 

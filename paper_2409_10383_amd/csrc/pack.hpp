@@ -24,7 +24,8 @@ struct z4c_pack {
     std::vector<XferItem> xfer;       // copies from active cells first, then from images
     int64_t nxfer_direct = 0;         // of which from active cells
     std::vector<ProlongItem> prol;
-    std::vector<ProlongGroup> pgrp;
+    std::vector<ProlongGroup> pgrp;   // parents by four (y and z, FP64), by two (y), then single
+    int64_t nparent = 0;              // coarse parents of grouped prolongations
     std::vector<ImageSlice> islice;
     std::vector<RegridDesc> regrid_desc;  // last regrid into this pack (kept for the upload)
     std::vector<int64_t> img_off;     // per block: offset of its coarse image, -1 if none

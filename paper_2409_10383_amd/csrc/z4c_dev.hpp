@@ -86,7 +86,9 @@ struct ProlongGroup {
     int64_t sh;           // shadow element offset of the union stencil origin
     int32_t block;        // destination block (field stride, row length)
     int32_t se;           // shadow box extent per axis
-    int32_t mask;         // bit (cz*4 + cy*2 + cx): child is a ghost to fill
+    int32_t mask;         // bit (cz*4 + cy*2 + cx): child is a ghost to fill; bits 8-15
+                          // the same for the parent one coarse cell further in y, and
+                          // bits 16-23, 24-31 for those further in z, in y and z
     int32_t fstride;      // field stride of the shadow box (elements)
 };
 
