@@ -125,7 +125,7 @@ __device__ __forceinline__ int work_index(int slot, int nwork)
     return x * per + k;
 }
 
-template <int N, class T, class C, int TX, int TY, int TZ, bool W>
+template <int N, class T, class C, int TX, int TY, int TZ, int SW>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w, C* tile, C* dxs,
                                            C* dys, C* adks, int* vtab);
 
@@ -143,7 +143,7 @@ template <class T> struct StageWaves {
 // W: the staged tiles are copied in 16-byte pieces (FP32 storage always;
 // FP64 when the ghost depth and the halo differ by an even count, which the
 // launch checks), else FP64 fields go as 4-byte halves.
-template <int N, class T, class C, int TX, int TY, int TZ, bool W>
+template <int N, class T, class C, int TX, int TY, int TZ, int SW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<T>::value))) void k_stage(
     const StageArgs a)
 {
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<
     __shared__ int vtab[27];       // the tile's block: halo offsets per direction
     if (!a.persistent) {
         const int w = work_index(blockIdx.x, a.nwork);
-        if (w < a.nwork) stage_tile<N, T, C, TX, TY, TZ, W>(a, a.work[w], tile, dxs, dys, adks, vtab);
+        if (w < a.nwork) stage_tile<N, T, C, TX, TY, TZ, SW>(a, a.work[w], tile, dxs, dys, adks, vtab);
         return;
     }
     // persistent: XCD x = blockIdx % 8 walks items x*per .. x*per+per-1
@@ -164,12 +164,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StageWaves<
     for (int k = k0; k < per; k += nk) {
         const int w = x * per + k;
         if (w >= a.nwork) break;
-        stage_tile<N, T, C, TX, TY, TZ, W>(a, a.work[w], tile, dxs, dys, adks, vtab);
+        stage_tile<N, T, C, TX, TY, TZ, SW>(a, a.work[w], tile, dxs, dys, adks, vtab);
         lds_barrier();
     }
 }
 
-template <int N, class T, class C, int TX, int TY, int TZ, bool W>
+template <int N, class T, class C, int TX, int TY, int TZ, int SW>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w, C* tile, C* dxs,
                                            C* dys, C* adks, int* vtab)
 {
@@ -278,13 +278,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     // two buffers the next field's copy is issued before the current field is
     // processed, so its latency overlaps the stencil work.
     constexpr int NBUF = StageLds<G, C>::NBUF;
-    constexpr int SLOT = sizeof(T) == 8 ? 16 : 4;        // bytes per lane and copy
+    // bytes per lane and copy (SW): a staged row splits into whole slots, each
+    // of one row's consecutive cells.  16-byte copies need a 16-byte aligned
+    // tile origin (E, every field base and the tile's x origin), which the
+    // launch checks; otherwise FP64 fields go as 4-byte halves and FP32 ones
+    // cell by cell
+    constexpr int SLOT = sizeof(T) == 8 ? 16 : SW;
+    constexpr bool wide = sizeof(T) == 4 || SW == 16;
+    static_assert(!wide || (G::SX * (int)sizeof(T)) % SLOT == 0, "copy slots must not cross a staged row");
     constexpr int NSLOT = G::NS * (int)sizeof(T) / SLOT;
     constexpr int NRS = (NSLOT + 255) / 256;
-    // 16-byte FP64 copies need a 16-byte aligned tile origin: E, every field
-    // base and the tile's x origin are even when the ghost depth and the halo
-    // differ by an even count (W); otherwise FP64 fields go as 4-byte halves
-    constexpr bool wide = W;
     // staged cells outside the block read a same-level neighbour directly
     // where the pack provides a virtual halo for that direction (the offset
     // table then points the block's ghosted index at the neighbour's cells);
@@ -581,18 +584,38 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     }
 }
 
+// FP32 copy width of a tile shape: 16 bytes where a staged row is a multiple
+// of four cells (the launch also needs a 16-byte aligned origin), else 4;
+// and the width when the origin is not aligned
+template <int N, int TX> struct Fp32Slot {
+    static constexpr int SX = TX + 2 * (N + 1);
+    static constexpr int best = SX % 4 == 0 ? 16 : 4;
+    static constexpr int fallback = 4;
+};
+
 template <int N, int TX, int TY, int TZ>
 static hipError_t launch_v(int prec, const StageArgs& a, int grid, hipStream_t s)
 {
+    const int R = N + 1;
     if (prec == 0) {
         // 16-byte FP64 copies when the ghost depth and the halo N+1 differ by
         // an even count
-        if (((a.g - (N + 1)) & 1) == 0)
-            hipLaunchKernelGGL((k_stage<N, double, double, TX, TY, TZ, true>), dim3(grid), dim3(256), 0, s, a);
+        if (((a.g - R) & 1) == 0)
+            hipLaunchKernelGGL((k_stage<N, double, double, TX, TY, TZ, 16>), dim3(grid), dim3(256), 0, s, a);
         else
-            hipLaunchKernelGGL((k_stage<N, double, double, TX, TY, TZ, false>), dim3(grid), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_stage<N, double, double, TX, TY, TZ, 4>), dim3(grid), dim3(256), 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_stage<N, float, float, TX, TY, TZ, true>), dim3(grid), dim3(256), 0, s, a);
+        // 16-byte FP32 copies: E = n + 2g a multiple of 4 cells (n is a
+        // multiple of 8: g even) and the tile origin i0 - R + g too (i0 is a
+        // multiple of 8)
+        using S = Fp32Slot<N, TX>;
+        if constexpr (S::best != 16) {
+            hipLaunchKernelGGL((k_stage<N, float, float, TX, TY, TZ, S::best>), dim3(grid), dim3(256), 0, s, a);
+        } else if ((a.g % 2 == 0) && ((a.g - R) % 4 == 0)) {
+            hipLaunchKernelGGL((k_stage<N, float, float, TX, TY, TZ, 16>), dim3(grid), dim3(256), 0, s, a);
+        } else {
+            hipLaunchKernelGGL((k_stage<N, float, float, TX, TY, TZ, S::fallback>), dim3(grid), dim3(256), 0, s, a);
+        }
     }
     return hipGetLastError();
 }
@@ -621,14 +644,16 @@ hipError_t launch_stage(int N, int prec, int variant, const StageArgs& a, int gr
     return hipErrorInvalidValue;
 }
 
-// resident workgroups per CU of a variant (for the persistent grid; the
-// FP64 kernels with 4-byte copies hold one workgroup per CU like the others)
+// resident workgroups per CU of a variant (for the persistent grid; taken
+// from the kernel with the widest copies the variant has: the FP64 kernels
+// hold one workgroup per CU either way)
 int stage_occupancy(int N, int prec, int variant)
 {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
 #define Z4C_OCC(NN, TT, X, Y, Z) \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_stage<NN, TT, TT, X, Y, Z, true>, 256, 0)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(                               \
+        &nb, k_stage<NN, TT, TT, X, Y, Z, sizeof(TT) == 8 ? 16 : Fp32Slot<NN, X>::best>, 256, 0)
 #define Z4C_OCCV(NN, TT)                                                     \
     switch (variant) {                                                        \
     case 0: Z4C_OCC(NN, TT, 8, 8, 4); break;                                  \

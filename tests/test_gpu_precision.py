@@ -64,6 +64,42 @@ def test_fp32_rhs_within_bound(name):
     print(name, "max err/bound:", float((err / bound).max()))
 
 
+@pytest.mark.parametrize("order", [6, 8])
+def test_fp32_every_tile_shape(order):
+    """FP32 storage in every tile shape and launch mode (the width of the
+    copies into LDS follows the shape and ghost depth: 16 bytes for the
+    6th-order tiles, 4 otherwise): the RHS within the derived bound of the
+    oracle, and the RHS and one RK4 step bitwise the same in every shape."""
+    g = order // 2 + 1
+    mesh = zi.uniform_mesh((2, 2, 2), 16, g, (-4.0,) * 3, (4.0,) * 3, zi.BC_OUTFLOW)
+    data = zi.add_perturbation(mesh, zi.brill_lindquist(mesh, [(1.0, (0.2, 0.0, 0.0))]), seed=3, amp=1e-4)
+    p = zi.params_default(order)
+    dt = 0.25 * mesh.dx0
+    om = oracle.OracleMesh(mesh)
+    ro = oracle.rhs(om, p, om.scatter(data))
+    bound = rhs_bound(order, mesh.dx0, ro, data)
+    first = None
+    for v in range(len(z().TILE_SHAPES)):
+        for pers in (False, True):
+            pk = z().Pack(mesh, p, z().FP32_MIXED)
+            pk.upload(z().REG_U, data)
+            pk.set_variant(v, pers)
+            pk.fill_ghosts()
+            rg = pk.split_interior(pk.rhs())
+            pk.rk4_step(dt, 1)
+            torch.cuda.synchronize()
+            st = pk.download(z().REG_U)
+            if first is None:
+                err = np.max([np.abs(a - b).reshape(22, -1).max(1) for a, b in zip(rg, ro)], axis=0)
+                assert np.all(err <= bound), [(f, err[f], bound[f]) for f in range(22) if err[f] > bound[f]]
+                first = (rg, st)
+            else:
+                for a, b in zip(rg, first[0]):
+                    np.testing.assert_array_equal(a, b)
+                for a, b in zip(st, first[1]):
+                    np.testing.assert_array_equal(a, b)
+
+
 def test_fp32_step_within_bound_and_accumulator_fp64():
     mesh, p, data, dt, _ = zi.workload("periodic16")
     nst = 2
