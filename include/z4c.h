@@ -208,13 +208,17 @@ int z4c_rhs(struct z4c_pack *pack, int32_t src_reg, void *rhs_out, void *stream)
  * boundary condition is USER, preceded by the ghost fill of the stage input
  * (where a block's neighbour region in some direction is one block of the
  * same level and size, the stage reads that neighbour's active cells
- * directly and those ghost cells are not written, except in directions with
- * an x component for FP32 storage or an odd FP64 ghost depth: there the
- * stage kernel writes such a neighbour's ghosts itself, into the register it
- * writes, and the fill of stages 2-4 leaves them alone when the previous
- * call of this function on the pack was the preceding stage, so the input
- * register must then hold what that stage wrote; z4c_fill_ghosts always
- * writes every ghost cell):
+ * directly and those ghost cells are not written; with outflow boundaries
+ * the same holds where the direction's y or z leaves the domain and the
+ * remaining components name such a block, or none, the read being clamped
+ * to the active range.  Two kinds of ghosts are written by the stage kernel
+ * itself, into the register it writes: a same-level neighbour's x-face
+ * ghosts for FP32 storage or an odd FP64 ghost depth, and the ghost columns
+ * beyond an outflow x face, in the block and in its same-level neighbours
+ * across y and z.  The fill of stages 2-4 leaves those alone when the
+ * previous call of this function on the pack was the preceding stage, so
+ * the input register must then hold what that stage wrote; z4c_fill_ghosts
+ * always writes every ghost cell):
  *   1: k1=F(U):  S1 = U + dt/2 k1, A  = U + dt/6 k1
  *   2: k2=F(S1): S2 = U + dt/2 k2, A += dt/3 k2
  *   3: k3=F(S2): S1 = U + dt k3,   A += dt/3 k3
@@ -223,7 +227,9 @@ int z4c_rhs(struct z4c_pack *pack, int32_t src_reg, void *rhs_out, void *stream)
  * chi/alpha floors on the written state.  A accumulates in double. */
 int z4c_rk4_stage(struct z4c_pack *pack, int32_t stage, double dt, void *stream);
 
-/* nsteps full RK4 steps of U (four stages each).  With Z4C_FLAG_GRAPH and a
+/* nsteps full RK4 steps of U (four stages each).  Without a graph, from the
+ * second step of the call on, stage 1's fill also leaves alone the ghosts
+ * of U that the previous step's stage 4 wrote.  With Z4C_FLAG_GRAPH and a
  * non-NULL stream, the four stages (ghost fills included) are captured once
  * into a hipGraph per (dt, stream) and replayed for every step.  With
  * Z4C_FLAG_CHECK_FINITE, after the steps every value of U's active cells is

@@ -455,76 +455,132 @@ int build_xlevel(z4c_pack* pk)
 // face it reads its own, or that neighbour's, x ghosts).  FP64 lanes that
 // are not 16-byte aligned (ghost depth and halo of different parity) copy
 // per half cell from the block itself: no direction is virtual or pushed.
-// Outflow boundaries: where every nonzero component of a direction with
-// dx = 0 leaves the domain, the outflow ghost is the block's own active cell
-// with y and z clamped to its active range (the block spans the domain edge),
-// so the stage reads that cell directly and the fill skips the direction too.
+// Outflow boundaries: a staged cell whose y or z lies beyond a domain face
+// takes the value of the nearest active cell along that axis, so a direction
+// whose y and z components leave the domain (dx = 0, or any dx where x
+// directions are read in place) reads the block across its remaining
+// components, the block itself where none remain, with y and z clamped to
+// the active range (cmask: y and z clamp bits per direction); the fill skips
+// those directions too.  Directions across an outflow x face cannot be
+// clamped per lane; there the zones on the face write the ghost columns
+// beyond it (omask) into their own block and into the same-level neighbours
+// across y and z whose ghosts reach their rows, the clamped rows beyond y and
+// z domain faces included, and the fill leaves those directions alone from
+// the second stage of a step on (fskip, with the pushed x directions).
 void build_virtual_halos(z4c_pack* pk)
 {
     const int nb = (int)pk->blk.size();
     const int g = pk->p.nghost, R = pk->p.fd_order / 2 + 1;
     pk->vnbr.assign((size_t)27 * nb, 0);
     pk->vmask.assign(nb, 0u);
-    pk->cmask.assign(nb, 0u);
+    pk->cmask.assign((size_t)2 * nb, 0u);
     pk->pmask.assign(nb, 0u);
+    pk->omask.assign(nb, 0u);
+    pk->fskip.assign(nb, 0u);
     pk->virt_x = 1;
+    pk->fill_pushed_empty = false;
     for (int b = 0; b < nb; ++b)
         for (int i = 0; i < 27; ++i) pk->vnbr[27 * b + i] = pk->bdev[b].off;
     const bool fp64 = pk->p.precision == Z4C_FP64;
     if (pk->p.bc == Z4C_BC_USER) return;
     if (fp64 && ((g - R) & 1)) return;
     if (!fp64 || (g & 1)) pk->virt_x = 0;
+    const bool outflow = pk->p.bc == Z4C_BC_OUTFLOW;
     std::map<std::tuple<int, int, int64_t, int64_t, int64_t>, int> at;   // (level, n, ilo) -> block
     for (int b = 0; b < nb; ++b) {
         const z4c_block& B = pk->blk[b];
         at[std::make_tuple(B.level, B.n, (int64_t)B.ilo[0], (int64_t)B.ilo[1], (int64_t)B.ilo[2])] = b;
     }
+    std::vector<uint32_t> same(nb, 0u);   // directions with a same-level neighbour of the same size
+    std::vector<std::array<uint8_t, 3>> face(nb);   // per axis: bit 0 low, bit 1 high face on the domain face
     for (int b = 0; b < nb; ++b) {
         const z4c_block& B = pk->blk[b];
         const BlockDev& D = pk->bdev[b];
+        for (int a = 0; a < 3; ++a) {
+            const int64_t N = (int64_t)pk->p.nroot[a] << B.level;
+            face[b][a] = (uint8_t)((B.ilo[a] == 0 ? 1 : 0) | ((int64_t)B.ilo[a] + B.n >= N ? 2 : 0));
+        }
         for (int dz = -1; dz <= 1; ++dz)
             for (int dy = -1; dy <= 1; ++dy)
                 for (int dx = -1; dx <= 1; ++dx) {
                     if (!dx && !dy && !dz) continue;
                     const int dd[3] = {dx, dy, dz};
-                    if (!dx && pk->p.bc == Z4C_BC_OUTFLOW) {
-                        bool all_out = true;
-                        for (int a = 1; a < 3; ++a) {
-                            const int64_t N = (int64_t)pk->p.nroot[a] << B.level;
-                            const int64_t Ja = (int64_t)B.ilo[a] + (int64_t)dd[a] * B.n;
-                            if (dd[a] && Ja >= 0 && Ja < N) all_out = false;
-                        }
-                        if (all_out) {
-                            const int idx = (dz + 1) * 9 + (dy + 1) * 3 + 1;
-                            pk->cmask[b] |= 1u << idx;
-                            pk->vmask[b] |= 1u << idx;
-                            continue;
-                        }
-                    }
-                    int64_t J[3];
-                    bool inside = true;
-                    for (int a = 0; a < 3; ++a) {
-                        const int64_t N = (int64_t)pk->p.nroot[a] << B.level;
-                        J[a] = (int64_t)B.ilo[a] + (int64_t)dd[a] * B.n;
-                        if (J[a] < 0 || J[a] >= N) {
-                            if (pk->p.bc != Z4C_BC_PERIODIC) inside = false;
-                            J[a] = ((J[a] % N) + N) % N;
-                        }
-                    }
-                    if (!inside) continue;
-                    auto it = at.find(std::make_tuple(B.level, B.n, J[0], J[1], J[2]));
-                    if (it == at.end()) continue;
-                    const BlockDev& T = pk->bdev[it->second];
-                    const int64_t E = D.E;
-                    const int64_t v = T.off - (int64_t)B.n * (dz * E * E + dy * E + dx);
-                    // element offsets of the staged cells stay within int32
-                    if (std::llabs(v - D.off) > ((int64_t)1 << 30)) continue;
                     const int idx = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+                    // outflow: drop the y and z components that leave the domain
+                    int ee[3] = {dx, dy, dz};
+                    uint32_t cy = 0, cz = 0;
+                    if (outflow) {
+                        for (int a = 1; a < 3; ++a)
+                            if (dd[a] && (face[b][a] >> (dd[a] > 0)) & 1) {
+                                ee[a] = 0;
+                                (a == 1 ? cy : cz) = 1u;
+                            }
+                        if (dx && (face[b][0] >> (dx > 0)) & 1) continue;   // across an outflow x face
+                    }
+                    const bool clamped = cy || cz;
+                    if (clamped && dx && !pk->virt_x) continue;
+                    int64_t v = D.off;
+                    if (ee[0] || ee[1] || ee[2]) {
+                        int64_t J[3];
+                        bool inside = true;
+                        for (int a = 0; a < 3; ++a) {
+                            const int64_t N = (int64_t)pk->p.nroot[a] << B.level;
+                            J[a] = (int64_t)B.ilo[a] + (int64_t)ee[a] * B.n;
+                            if (J[a] < 0 || J[a] >= N) {
+                                if (pk->p.bc != Z4C_BC_PERIODIC) inside = false;
+                                J[a] = ((J[a] % N) + N) % N;
+                            }
+                        }
+                        if (!inside) continue;
+                        auto it = at.find(std::make_tuple(B.level, B.n, J[0], J[1], J[2]));
+                        if (it == at.end()) continue;
+                        const BlockDev& T = pk->bdev[it->second];
+                        const int64_t E = D.E;
+                        v = T.off - (int64_t)B.n * (ee[2] * E * E + ee[1] * E + ee[0]);
+                        // element offsets of the staged cells stay within int32
+                        if (std::llabs(v - D.off) > ((int64_t)1 << 30)) continue;
+                        if (!clamped) same[b] |= 1u << idx;
+                    }
                     pk->vnbr[27 * b + idx] = v;
+                    pk->cmask[2 * b] |= cy << idx;
+                    pk->cmask[2 * b + 1] |= cz << idx;
                     if (dx && !pk->virt_x) pk->pmask[b] |= 1u << idx;
                     else pk->vmask[b] |= 1u << idx;
                 }
     }
+    if (outflow) {
+        for (int b = 0; b < nb; ++b) {
+            const uint32_t xf = face[b][0] & 3u;
+            if (!xf) continue;
+            // pusher: faces, and the blocks across (0, ey, ez) it writes into
+            uint32_t om = xf | (uint32_t)(face[b][1] & 3u) << 2 | (uint32_t)(face[b][2] & 3u) << 4;
+            for (int e = 0; e < 9; ++e) {
+                const int idx = e * 3 + 1;   // direction (0, e % 3 - 1, e / 3 - 1)
+                if (e == 4 || ((same[b] >> idx) & 1u)) om |= 1u << (8 + e);
+            }
+            pk->omask[b] = om;
+            // receiver: a direction across an outflow x face takes its values
+            // from the block across its y and z components that stay inside
+            // the domain (the block itself if none does)
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; dx += 2) {
+                        if (!((xf >> (dx > 0)) & 1u)) continue;
+                        const int sy = (dy && !((face[b][1] >> (dy > 0)) & 1)) ? dy : 0;
+                        const int sz = (dz && !((face[b][2] >> (dz > 0)) & 1)) ? dz : 0;
+                        const int sidx = (sz + 1) * 9 + (sy + 1) * 3 + 1;
+                        if ((sy || sz) && !((same[b] >> sidx) & 1u)) continue;
+                        pk->fskip[b] |= 1u << ((dz + 1) * 9 + (dy + 1) * 3 + (dx + 1));
+                    }
+        }
+    }
+    const uint32_t all = ((1u << 27) - 1) & ~(1u << 13);
+    bool empty = true;
+    for (int b = 0; b < nb; ++b) {
+        pk->fskip[b] |= pk->pmask[b];
+        if (((pk->vmask[b] | pk->fskip[b]) & all) != all) empty = false;
+    }
+    pk->fill_pushed_empty = empty;
 }
 
 // side stream and its fork/join events (multi-level packs)
@@ -723,8 +779,10 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
     pk->ws_regrid = o; o = align256(o + sizeof(RegridDesc) * nblocks);
     pk->ws_vnbr = o;   o = align256(o + sizeof(int64_t) * 27 * nblocks);
     pk->ws_vmask = o;  o = align256(o + sizeof(uint32_t) * nblocks);
-    pk->ws_cmask = o;  o = align256(o + sizeof(uint32_t) * nblocks);
+    pk->ws_cmask = o;  o = align256(o + sizeof(uint32_t) * 2 * nblocks);
     pk->ws_pmask = o;  o = align256(o + sizeof(uint32_t) * nblocks);
+    pk->ws_omask = o;  o = align256(o + sizeof(uint32_t) * nblocks);
+    pk->ws_fskip = o;  o = align256(o + sizeof(uint32_t) * nblocks);
     pk->ws_track = o;  o = align256(o + sizeof(double) * 9 * Z4C_MAXTRACK);
     pk->ws_flag = o;   o = align256(o + sizeof(int32_t));
     pk->ws_total = o;
@@ -800,6 +858,12 @@ int z4c_pack_bind(z4c_pack* pk, void* const regs[Z4C_NREG], void* workspace, siz
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ws + pk->ws_pmask, pk->pmask.data(), sizeof(uint32_t) * pk->pmask.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + pk->ws_omask, pk->omask.data(), sizeof(uint32_t) * pk->omask.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + pk->ws_fskip, pk->fskip.data(), sizeof(uint32_t) * pk->fskip.size(),
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !pk->islice.empty())
         e = hipMemcpyAsync(ws + pk->ws_islice, pk->islice.data(), sizeof(ImageSlice) * pk->islice.size(),
@@ -891,7 +955,10 @@ static int fill_impl(z4c_pack* pk, int32_t reg, void* stream, bool virt, bool pu
     if (pk->p.bc == Z4C_BC_USER) return Z4C_OK;
     FillArgs a;
     a.skip = virt ? reinterpret_cast<const uint32_t*>(pk->ws + pk->ws_vmask) : nullptr;
-    a.skip2 = (virt && pushed) ? reinterpret_cast<const uint32_t*>(pk->ws + pk->ws_pmask) : nullptr;
+    a.skip2 = (virt && pushed) ? reinterpret_cast<const uint32_t*>(pk->ws + pk->ws_fskip) : nullptr;
+    // every ghost cell the same-level fill would write is read in place or
+    // was written by the stage kernel that produced the register
+    const bool same_empty = virt && pushed && pk->fill_pushed_empty;
     a.reg = pk->reg[reg];
     a.blocks = reinterpret_cast<const BlockDev*>(pk->ws + pk->ws_blocks);
     a.map = reinterpret_cast<const int32_t*>(pk->ws + pk->ws_map);
@@ -934,7 +1001,7 @@ static int fill_impl(z4c_pack* pk, int32_t reg, void* stream, bool virt, bool pu
     if (fork) {
         e = hipEventRecord(pk->fork_ev, s);
         if (e == hipSuccess) e = hipStreamWaitEvent(pk->side, pk->fork_ev, 0);
-        if (e == hipSuccess) e = launch_fill(pk->p.precision, a, (int)pk->blk.size(), pk->side);
+        if (e == hipSuccess && !same_empty) e = launch_fill(pk->p.precision, a, (int)pk->blk.size(), pk->side);
         if (e == hipSuccess) {
             x.xfer = xf;
             x.nxfer = ndir;
@@ -951,7 +1018,7 @@ static int fill_impl(z4c_pack* pk, int32_t reg, void* stream, bool virt, bool pu
         if (e == hipSuccess) e = j;
         if (e == hipSuccess) e = launch_xlevel(pk->p.precision, x, s, XL_PROLONG);
     } else {
-        e = launch_fill(pk->p.precision, a, (int)pk->blk.size(), s);
+        if (!same_empty) e = launch_fill(pk->p.precision, a, (int)pk->blk.size(), s);
         if (e == hipSuccess && pk->multilevel)
             e = launch_xlevel(pk->p.precision, x, s, XL_RESTRICT | XL_XFER | XL_PROLONG);
     }
@@ -982,6 +1049,7 @@ static StageArgs stage_args(z4c_pack* pk)
     a.vnbr = reinterpret_cast<const int64_t*>(pk->ws + pk->ws_vnbr);
     a.cmask = reinterpret_cast<const uint32_t*>(pk->ws + pk->ws_cmask);
     a.pmask = reinterpret_cast<const uint32_t*>(pk->ws + pk->ws_pmask);
+    a.omask = reinterpret_cast<const uint32_t*>(pk->ws + pk->ws_omask);
     a.virt_x = pk->virt_x;
     return a;
 }
@@ -1002,17 +1070,14 @@ int z4c_rhs(z4c_pack* pk, int32_t src_reg, void* rhs_out, void* stream)
     return Z4C_OK;
 }
 
-int z4c_rk4_stage(z4c_pack* pk, int32_t stage, double dt, void* stream)
+// chained: the stage kernel that ran last on the pack wrote the stage's input
+// register, so the ghosts it wrote (pushed x-face ghosts, outflow x faces)
+// are current and the fill leaves them alone
+static int rk4_stage_impl(z4c_pack* pk, int32_t stage, double dt, void* stream, bool chained)
 {
-    if (!pk) return Z4C_EINVAL;
-    if (stage < 1 || stage > 4) return fail(pk, Z4C_EINVAL, "bad stage %d", stage);
-    if (!std::isfinite(dt)) return fail(pk, Z4C_EINVAL, "dt not finite");
-    if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
     static const int src_of[5] = {0, Z4C_REG_U, Z4C_REG_S1, Z4C_REG_S2, Z4C_REG_S1};
     static const int dst_of[5] = {0, Z4C_REG_S1, Z4C_REG_S2, Z4C_REG_S1, Z4C_REG_U};
-    // stages 2-4 read the register the previous stage wrote, x-face ghosts
-    // of same-level neighbours included, when that stage ran last
-    int rc = fill_impl(pk, src_of[stage], stream, true, stage >= 2 && pk->last_stage == stage - 1);
+    int rc = fill_impl(pk, src_of[stage], stream, true, chained);
     pk->last_stage = 0;
     if (rc) return rc;
     if (pk->ntrack > 0) {
@@ -1030,6 +1095,17 @@ int z4c_rk4_stage(z4c_pack* pk, int32_t stage, double dt, void* stream)
     if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "stage launch: %s", hipGetErrorString(e));
     pk->last_stage = stage;
     return Z4C_OK;
+}
+
+int z4c_rk4_stage(z4c_pack* pk, int32_t stage, double dt, void* stream)
+{
+    if (!pk) return Z4C_EINVAL;
+    if (stage < 1 || stage > 4) return fail(pk, Z4C_EINVAL, "bad stage %d", stage);
+    if (!std::isfinite(dt)) return fail(pk, Z4C_EINVAL, "dt not finite");
+    if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
+    // stages 2-4 read the register the previous stage wrote when that stage
+    // ran last; stage 1 reads U, which the caller may have changed since
+    return rk4_stage_impl(pk, stage, dt, stream, stage >= 2 && pk->last_stage == stage - 1);
 }
 
 // with Z4C_FLAG_CHECK_FINITE: every value of U's active cells finite?
@@ -1094,9 +1170,12 @@ static int rk4_steps(z4c_pack* pk, double dt, int32_t nsteps, void* stream)
         }
         return Z4C_OK;
     }
+    // within the call, a step's stage 1 reads the U the previous step's
+    // stage 4 wrote
     for (int n = 0; n < nsteps; ++n)
         for (int st = 1; st <= 4; ++st) {
-            int rc = z4c_rk4_stage(pk, st, dt, stream);
+            const bool chained = st >= 2 ? pk->last_stage == st - 1 : (n > 0 && pk->last_stage == 4);
+            int rc = rk4_stage_impl(pk, st, dt, stream, chained);
             if (rc) return rc;
         }
     return Z4C_OK;

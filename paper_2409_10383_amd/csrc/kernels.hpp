@@ -14,8 +14,11 @@ struct StageArgs {
     const BlockDev* blocks;
     const WorkItem* work;
     const int64_t* vnbr;      // per block, 27 direction offsets of the staged halo
-    const uint32_t* cmask;    // per block, directions read clamped (outflow)
+    const uint32_t* cmask;    // per block (2 b, 2 b + 1), directions read with y, z clamped (outflow)
     const uint32_t* pmask;    // per block, x directions pushed to a same-level neighbour
+    const uint32_t* omask;    // per block, outflow x faces pushed: bits 0, 1 low / high x face;
+                              // 2-5 low / high y, z faces on the domain face; 8 + e: target
+                              // block across (0, e % 3 - 1, e / 3 - 1) (e = 4: the block itself)
     int32_t virt_x;           // 0: a staged cell's halo direction ignores x
     ParamsDev P;
     double dt;
@@ -37,7 +40,8 @@ struct FillArgs {
     int32_t nroot[3];
     int32_t maxghost;         // ghost cells of the largest block
     const uint32_t* skip;     // per block, directions left alone (virtual halos); null = none
-    const uint32_t* skip2;    // per block, further directions left alone (pushed); null = none
+    const uint32_t* skip2;    // per block, further directions left alone (written by the
+                              // stage kernel that produced the register); null = none
 };
 
 // Restriction window of coarse cell kc (0 <= kc < n/2) inside a fine block

@@ -37,11 +37,16 @@ struct z4c_pack {
     size_t ws_regrid = 0, ws_vnbr = 0, ws_vmask = 0;
     std::vector<int64_t> vnbr;    // virtual halos: 27 offsets per block
     std::vector<uint32_t> vmask;  // directions the stage path's fill skips, per block
-    std::vector<uint32_t> cmask;  // of those, the clamped outflow directions
+    std::vector<uint32_t> cmask;  // of those, per block the directions read with y (2 b) and z (2 b + 1) clamped
     size_t ws_cmask = 0;
     int virt_x = 1;               // 1: directions with dx != 0 are read in place too
     std::vector<uint32_t> pmask;  // per block, x directions whose ghosts the stage kernel pushes
     size_t ws_pmask = 0;
+    std::vector<uint32_t> omask;  // per block, outflow x faces whose ghost columns the stage kernel writes
+    size_t ws_omask = 0;
+    std::vector<uint32_t> fskip;  // per block, directions written by the previous stage kernel
+    size_t ws_fskip = 0;
+    bool fill_pushed_empty = false;   // after a stage, the same-level fill has nothing left to do
     int last_stage = 0;           // last RK stage run on the pack (0: none, or other work since)
     // puncture tracker: device state (x, k_prev, acc) per puncture in the workspace
     int ntrack = 0;

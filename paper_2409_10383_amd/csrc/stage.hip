@@ -297,9 +297,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
     // table there instead of waiting on one global load per slot)
     if (t < 27) vtab[t] = (int)(a.vnbr[(int64_t)w.block * 27 + t] - B.off);
     lds_barrier();
-    // clamped outflow directions read the block's own active cells, with the
-    // y and z of the staged cell clamped to the active range
-    const uint32_t cm = a.cmask[w.block];
+    // outflow directions whose y or z leaves the domain read the block across
+    // the remaining components (the table's offset), with that y or z of the
+    // staged cell clamped to the active range
+    const uint32_t cmy = a.cmask[2 * w.block], cmz = a.cmask[2 * w.block + 1];
     int soff[NRS];
 #pragma unroll
     for (int r = 0; r < NRS; ++r) {
@@ -311,9 +312,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
         // stays one block's memory
         const int dir = ((lz < 0 ? 0 : (lz >= n ? 2 : 1)) * 3 + (ly < 0 ? 0 : (ly >= n ? 2 : 1))) * 3 +
                         (a.virt_x ? (lx < 0 ? 0 : (lx >= n ? 2 : 1)) : 1);
-        const bool clamp = (cm >> dir) & 1u;
-        const int cy = clamp ? (ly < 0 ? 0 : (ly >= n ? n - 1 : ly)) : ly;
-        const int cz = clamp ? (lz < 0 ? 0 : (lz >= n ? n - 1 : lz)) : lz;
+        const int cy = ((cmy >> dir) & 1u) ? (ly < 0 ? 0 : (ly >= n ? n - 1 : ly)) : ly;
+        const int cz = ((cmz >> dir) & 1u) ? (lz < 0 ? 0 : (lz >= n ? n - 1 : lz)) : lz;
         soff[r] = vtab[dir] + ((cz + g) * E + (cy + g)) * E + (lx + g);
     }
     auto issue = [&](int f, C* buf) {
@@ -580,6 +580,49 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WorkItem w,
             T* __restrict__ gh = (T*)a.dst + B.off + vtab[d] + cz;
 #pragma unroll
             for (int f = 0; f < NF; ++f) gh[f * slab] = (T)out[f];
+        }
+    }
+    // A tile on an outflow x face: its face zones are the nearest active cells
+    // of the g ghost columns beyond them in their rows and, at a y or z domain
+    // face, of those of the rows beyond that face.  The face zones put their
+    // new state in their own slots of the advection store (read above, each
+    // thread its own slot only), and the workgroup writes those ghost cells in
+    // this block and in the same-level neighbours across y and z whose ghost
+    // layers hold them, one thread per ghost cell.
+    const uint32_t om = a.omask[w.block];
+#pragma unroll 1
+    for (int side = 0; side < 2; ++side) {
+        if (!((om >> side) & 1u) || (side ? w.i0 + TX != n : w.i0 != 0)) continue;
+        const int fx = side ? TX - 1 : 0;    // the tile's face column
+        if (tx == fx) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) adks[f * 256 + t] = (C)(T)out[f];
+        }
+        lds_barrier();
+        const int xg = side ? n + g : 0;     // first ghost column, ghosted index
+        const int ya = (w.j0 == 0 && (om & 4u)) ? -g : w.j0;
+        const int yb = (w.j0 + TY == n && (om & 8u)) ? n + g - 1 : w.j0 + TY - 1;
+        const int za = (w.k0 == 0 && (om & 16u)) ? -g : w.k0;
+        const int zb = (w.k0 + TZ == n && (om & 32u)) ? n + g - 1 : w.k0 + TZ - 1;
+#pragma unroll 1
+        for (int e = 0; e < 9; ++e) {
+            if (!((om >> (8 + e)) & 1u)) continue;
+            const int ey = e % 3 - 1, ez = e / 3 - 1;
+            // rows and planes of the target's ghosted range, in this block's frame
+            const int y0 = max(ya, ey * n - g), y1 = min(yb, ey * n + n + g - 1);
+            const int z0 = max(za, ez * n - g), z1 = min(zb, ez * n + n + g - 1);
+            if (y0 > y1 || z0 > z1) continue;
+            const int ny = y1 - y0 + 1, ncell = (z1 - z0 + 1) * ny * g;
+            T* __restrict__ tb = (T*)a.dst + B.off + vtab[e * 3 + 1] + xg;
+            for (int q = t; q < ncell; q += 256) {
+                const int xc = q % g, r = q / g, yy = y0 + r % ny, zz = z0 + r / ny;
+                const int sy = min(max(yy, w.j0), w.j0 + TY - 1) - w.j0;
+                const int sz = min(max(zz, w.k0), w.k0 + TZ - 1) - w.k0;
+                const C* __restrict__ sv = adks + (sz * TY + sy) * TX + fx;
+                T* __restrict__ gh = tb + ((int64_t)(zz + g) * E + (yy + g)) * E + xc;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) gh[f * slab] = (T)sv[f * 256];
+            }
         }
     }
 }
