@@ -492,6 +492,7 @@ void build_virtual_halos(z4c_pack* pk)
         at[std::make_tuple(B.level, B.n, (int64_t)B.ilo[0], (int64_t)B.ilo[1], (int64_t)B.ilo[2])] = b;
     }
     std::vector<uint32_t> same(nb, 0u);   // directions with a same-level neighbour of the same size
+    std::vector<int> nbr((size_t)27 * nb, -1);   // that neighbour
     std::vector<std::array<uint8_t, 3>> face(nb);   // per axis: bit 0 low, bit 1 high face on the domain face
     for (int b = 0; b < nb; ++b) {
         const z4c_block& B = pk->blk[b];
@@ -539,7 +540,10 @@ void build_virtual_halos(z4c_pack* pk)
                         v = T.off - (int64_t)B.n * (ee[2] * E * E + ee[1] * E + ee[0]);
                         // element offsets of the staged cells stay within int32
                         if (std::llabs(v - D.off) > ((int64_t)1 << 30)) continue;
-                        if (!clamped) same[b] |= 1u << idx;
+                        if (!clamped) {
+                            same[b] |= 1u << idx;
+                            nbr[(size_t)27 * b + idx] = it->second;
+                        }
                     }
                     pk->vnbr[27 * b + idx] = v;
                     pk->cmask[2 * b] |= cy << idx;
@@ -548,15 +552,47 @@ void build_virtual_halos(z4c_pack* pk)
                     else pk->vmask[b] |= 1u << idx;
                 }
     }
+    // Without x directions read in place, a staged cell beyond an x face and
+    // a y or z face takes its direction from y and z alone: it reads the x
+    // ghosts of the block across (0, dy, dz) where that direction is read in
+    // place (or its own, clamped).  The block's own ghosts in (dx, dy, dz)
+    // are then never read: the fill skips them and nothing writes them.
+    // A block pushes into a neighbour's ghosts of direction (-dx, -dy, -dz)
+    // only where that neighbour reads them, and skips its own (dx, dy, dz)
+    // ghosts in the fill where it never reads them or the neighbour there
+    // pushes them (pmask: pusher role; recv: receiver role).
+    std::vector<uint32_t> recv = pk->pmask;
+    if (!pk->virt_x) {
+        const std::vector<uint32_t> v0 = pk->vmask, p0 = pk->pmask;
+        auto reads = [&](int b, int idx) {   // block b reads its ghosts of direction idx
+            const int dx = idx % 3 - 1, e = idx - dx;   // e: the direction with dx = 0
+            return e == 13 || !((v0[b] >> e) & 1u);
+        };
+        for (int b = 0; b < nb; ++b) {
+            uint32_t push = 0, skip = 0;
+            for (int idx = 0; idx < 27; ++idx) {
+                if (idx % 3 == 1) continue;   // dx = 0
+                if (!reads(b, idx)) pk->vmask[b] |= 1u << idx;
+                else if ((p0[b] >> idx) & 1u) skip |= 1u << idx;
+                if (((p0[b] >> idx) & 1u) && reads(nbr[(size_t)27 * b + idx], 26 - idx)) push |= 1u << idx;
+            }
+            pk->pmask[b] = push;
+            recv[b] = skip;
+        }
+    }
     if (outflow) {
         for (int b = 0; b < nb; ++b) {
             const uint32_t xf = face[b][0] & 3u;
             if (!xf) continue;
             // pusher: faces, and the blocks across (0, ey, ez) it writes into
-            uint32_t om = xf | (uint32_t)(face[b][1] & 3u) << 2 | (uint32_t)(face[b][2] & 3u) << 4;
-            for (int e = 0; e < 9; ++e) {
-                const int idx = e * 3 + 1;   // direction (0, e % 3 - 1, e / 3 - 1)
-                if (e == 4 || ((same[b] >> idx) & 1u)) om |= 1u << (8 + e);
+            // (without x directions read in place only its own rows are read)
+            uint32_t om = xf | 1u << (8 + 4);
+            if (pk->virt_x) {
+                om |= (uint32_t)(face[b][1] & 3u) << 2 | (uint32_t)(face[b][2] & 3u) << 4;
+                for (int e = 0; e < 9; ++e) {
+                    const int idx = e * 3 + 1;   // direction (0, e % 3 - 1, e / 3 - 1)
+                    if ((same[b] >> idx) & 1u) om |= 1u << (8 + e);
+                }
             }
             pk->omask[b] = om;
             // receiver: a direction across an outflow x face takes its values
@@ -566,6 +602,7 @@ void build_virtual_halos(z4c_pack* pk)
                 for (int dy = -1; dy <= 1; ++dy)
                     for (int dx = -1; dx <= 1; dx += 2) {
                         if (!((xf >> (dx > 0)) & 1u)) continue;
+                        if (!pk->virt_x && (dy || dz)) continue;   // never read, or filled
                         const int sy = (dy && !((face[b][1] >> (dy > 0)) & 1)) ? dy : 0;
                         const int sz = (dz && !((face[b][2] >> (dz > 0)) & 1)) ? dz : 0;
                         const int sidx = (sz + 1) * 9 + (sy + 1) * 3 + 1;
@@ -577,7 +614,7 @@ void build_virtual_halos(z4c_pack* pk)
     const uint32_t all = ((1u << 27) - 1) & ~(1u << 13);
     bool empty = true;
     for (int b = 0; b < nb; ++b) {
-        pk->fskip[b] |= pk->pmask[b];
+        pk->fskip[b] |= recv[b];
         if (((pk->vmask[b] | pk->fskip[b]) & all) != all) empty = false;
     }
     pk->fill_pushed_empty = empty;

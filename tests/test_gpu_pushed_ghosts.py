@@ -79,9 +79,13 @@ def test_steps_in_one_call_equal_steps_in_separate_calls(case):
 
 @pytest.mark.parametrize("prec,order,g", [(0, 6, 4), (0, 8, 5), (1, 6, 4)])
 def test_outflow_x_face_ghosts_written_by_the_last_stage(prec, order, g):
-    """After a step, the ghost columns beyond the outflow x faces of U (edges
-    and corners included) hold what a full fill writes: the last stage wrote
-    them."""
+    """After a step, the ghost columns beyond the outflow x faces of U hold
+    what a full fill writes: the last stage wrote them.  Edges and corners
+    included where x directions are read in place (FP64, even ghost depth);
+    with the x halos read from the block's own ghosts (FP32 storage, odd
+    ghost depth) a staged cell beyond a y or z face takes its x ghosts from
+    the block across that face or from the clamped row, so only the block's
+    own rows are read and written."""
     mesh = mesh_of("uniform", g)
     pk = z().Pack(mesh, zi.params_default(order), prec)
     pk.upload(z().REG_U, data_of(mesh))
@@ -101,7 +105,9 @@ def test_outflow_x_face_ghosts_written_by_the_last_stage(prec, order, g):
             cols.append(slice(0, g))
         if ilo + n == nx:
             cols.append(slice(n + g, n + 2 * g))
+        rows = slice(None) if (prec == 0 and g % 2 == 0) else slice(g, g + n)
         for c in cols:
             nface += 1
-            np.testing.assert_array_equal(before[b][:, :, :, c], after[b][:, :, :, c], err_msg=f"block {b}")
+            np.testing.assert_array_equal(before[b][:, rows, rows, c], after[b][:, rows, rows, c],
+                                          err_msg=f"block {b}")
     assert nface == 32
