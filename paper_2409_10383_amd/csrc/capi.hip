@@ -929,8 +929,7 @@ int z4c_pack_bind(z4c_pack* pk, void* const regs[Z4C_NREG], void* workspace, siz
     // a step graph captured against the previous registers / workspace holds
     // their addresses in its kernel arguments: drop it, the next graph step
     // captures again
-    if (pk->gexec) { hipGraphExecDestroy(pk->gexec); pk->gexec = nullptr; }
-    if (pk->graph) { hipGraphDestroy(pk->graph); pk->graph = nullptr; }
+    drop_graphs(pk);
     for (int r = 0; r < Z4C_NREG; ++r) pk->reg[r] = regs[r];
     pk->ws = ws;
     pk->bound = true;
@@ -942,8 +941,7 @@ int z4c_pack_bind(z4c_pack* pk, void* const regs[Z4C_NREG], void* workspace, siz
 void z4c_pack_destroy(z4c_pack* pk)
 {
     if (!pk) return;
-    if (pk->gexec) hipGraphExecDestroy(pk->gexec);
-    if (pk->graph) hipGraphDestroy(pk->graph);
+    drop_graphs(pk);
     release_side(pk);
     for (auto& e : pk->ev) {
         hipEventDestroy(e.a);
@@ -1179,31 +1177,52 @@ static int rk4_steps(z4c_pack* pk, double dt, int32_t nsteps, void* stream)
     if (!pk->bound) return fail(pk, Z4C_ESTATE, "pack not bound");
     hipStream_t s = as_stream(stream);
     if ((pk->p.flags & Z4C_FLAG_GRAPH) && s != nullptr && nsteps > 0) {
-        // one captured graph of the four stages (ghost fills included), replayed
-        if (!pk->gexec || pk->graph_dt != dt || pk->graph_stream != s) {
-            if (pk->gexec) { hipGraphExecDestroy(pk->gexec); pk->gexec = nullptr; }
-            if (pk->graph) { hipGraphDestroy(pk->graph); pk->graph = nullptr; }
+        // the four stages (ghost fills included) captured once, replayed: the
+        // first step of a call from `graph`, later ones from `graph2`, whose
+        // stage 1 finds the ghosts of U the previous step's stage 4 wrote
+        if (!pk->gexec || !pk->gexec2 || pk->graph_dt != dt || pk->graph_stream != s) {
+            drop_graphs(pk);
             const bool prof = pk->prof;
             pk->prof = false;
-            hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-            if (e != hipSuccess) { pk->prof = prof; return fail(pk, Z4C_EDEVICE, "capture: %s", hipGetErrorString(e)); }
-            int rc = Z4C_OK;
-            for (int st = 1; st <= 4 && rc == Z4C_OK; ++st) rc = z4c_rk4_stage(pk, st, dt, stream);
-            hipGraph_t gr = nullptr;
-            e = hipStreamEndCapture(s, &gr);
+            for (int g = 0; g < 2; ++g) {
+                hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) {
+                    pk->prof = prof;
+                    drop_graphs(pk);
+                    return fail(pk, Z4C_EDEVICE, "capture: %s", hipGetErrorString(e));
+                }
+                int rc = Z4C_OK;
+                for (int st = 1; st <= 4 && rc == Z4C_OK; ++st)
+                    rc = st == 1 ? rk4_stage_impl(pk, 1, dt, stream, g == 1) : z4c_rk4_stage(pk, st, dt, stream);
+                hipGraph_t gr = nullptr;
+                e = hipStreamEndCapture(s, &gr);
+                if (rc == Z4C_OK && e != hipSuccess) rc = fail(pk, Z4C_EDEVICE, "end capture: %s", hipGetErrorString(e));
+                hipGraphExec_t ex = nullptr;
+                if (rc == Z4C_OK) {
+                    e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+                    if (e != hipSuccess) rc = fail(pk, Z4C_EDEVICE, "instantiate: %s", hipGetErrorString(e));
+                }
+                if (rc) {
+                    if (gr) hipGraphDestroy(gr);
+                    pk->prof = prof;
+                    drop_graphs(pk);
+                    return rc;
+                }
+                (g ? pk->graph2 : pk->graph) = gr;
+                (g ? pk->gexec2 : pk->gexec) = ex;
+            }
             pk->prof = prof;
-            if (rc) { if (gr) hipGraphDestroy(gr); return rc; }
-            if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "end capture: %s", hipGetErrorString(e));
-            e = hipGraphInstantiate(&pk->gexec, gr, nullptr, nullptr, 0);
-            if (e != hipSuccess) { hipGraphDestroy(gr); return fail(pk, Z4C_EDEVICE, "instantiate: %s", hipGetErrorString(e)); }
-            pk->graph = gr;
             pk->graph_dt = dt;
             pk->graph_stream = s;
         }
         for (int n = 0; n < nsteps; ++n) {
             ProfScope ps(pk, s, 2);
-            hipError_t e = hipGraphLaunch(pk->gexec, s);
-            if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "graph launch: %s", hipGetErrorString(e));
+            hipError_t e = hipGraphLaunch(n ? pk->gexec2 : pk->gexec, s);
+            if (e != hipSuccess) {
+                pk->last_stage = 0;
+                return fail(pk, Z4C_EDEVICE, "graph launch: %s", hipGetErrorString(e));
+            }
+            pk->last_stage = 4;
         }
         return Z4C_OK;
     }
@@ -1235,8 +1254,7 @@ int z4c_set_variant(z4c_pack* pk, int32_t variant, int32_t persistent, void* str
         const int occ = stage_occupancy(pk->p.fd_order / 2, pk->p.precision, variant);
         pk->grid_persistent = std::min<int>((int)pk->work.size(), ncu * occ);
     }
-    if (pk->gexec) { hipGraphExecDestroy(pk->gexec); pk->gexec = nullptr; }
-    if (pk->graph) { hipGraphDestroy(pk->graph); pk->graph = nullptr; }
+    drop_graphs(pk);
     if (pk->bound) {
         hipError_t e = hipMemcpyAsync(pk->ws + pk->ws_work, pk->work.data(), sizeof(WorkItem) * pk->work.size(),
                                       hipMemcpyHostToDevice, as_stream(stream));

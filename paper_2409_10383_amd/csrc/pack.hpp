@@ -70,9 +70,13 @@ struct z4c_pack {
     int variant = 0;
     bool persistent = false;
     int grid_persistent = 0;
-    // captured RK4 step (hipGraph), valid for one (dt, stream)
+    // captured RK4 step (hipGraph), valid for one (dt, stream); graph2: the
+    // same step for the second and later steps of a call (its stage 1 finds
+    // the ghosts the previous step's stage 4 wrote)
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph2 = nullptr;
+    hipGraphExec_t gexec2 = nullptr;
     double graph_dt = 0.0;
     hipStream_t graph_stream = nullptr;
     // multi-level packs: the same-level fill runs on a side stream beside the
@@ -85,6 +89,17 @@ struct z4c_pack {
     std::vector<EvPair> ev;
     double prof_acc[6] = {0, 0, 0, 0, 0, 0};
 };
+
+// drop the captured step graphs (their kernel arguments hold the registers,
+// workspace, launch variant and tracker count they were captured with)
+inline void drop_graphs(z4c_pack* pk)
+{
+    if (pk->gexec) { (void)hipGraphExecDestroy(pk->gexec); pk->gexec = nullptr; }
+    if (pk->graph) { (void)hipGraphDestroy(pk->graph); pk->graph = nullptr; }
+    if (pk->gexec2) { (void)hipGraphExecDestroy(pk->gexec2); pk->gexec2 = nullptr; }
+    if (pk->graph2) { (void)hipGraphDestroy(pk->graph2); pk->graph2 = nullptr; }
+}
+
 
 namespace z4c_host {
 

@@ -595,8 +595,7 @@ int z4c_tracker_set(z4c_pack* pk, int32_t n, const double* pos, void* stream)
     if (e != hipSuccess) return fail(pk, Z4C_EDEVICE, "tracker upload: %s", hipGetErrorString(e));
     pk->ntrack = n;
     // a captured step graph does not hold the tracker launches of the new count
-    if (pk->gexec) { (void)hipGraphExecDestroy(pk->gexec); pk->gexec = nullptr; }
-    if (pk->graph) { (void)hipGraphDestroy(pk->graph); pk->graph = nullptr; }
+    drop_graphs(pk);
     return Z4C_OK;
 }
 
