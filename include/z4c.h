@@ -227,11 +227,13 @@ int z4c_rhs(struct z4c_pack *pack, int32_t src_reg, void *rhs_out, void *stream)
  * chi/alpha floors on the written state.  A accumulates in double. */
 int z4c_rk4_stage(struct z4c_pack *pack, int32_t stage, double dt, void *stream);
 
-/* nsteps full RK4 steps of U (four stages each).  Without a graph, from the
- * second step of the call on, stage 1's fill also leaves alone the ghosts
- * of U that the previous step's stage 4 wrote.  With Z4C_FLAG_GRAPH and a
- * non-NULL stream, the four stages (ghost fills included) are captured once
- * into a hipGraph per (dt, stream) and replayed for every step.  With
+/* nsteps full RK4 steps of U (four stages each).  From the second step of
+ * the call on, stage 1's fill also leaves alone the ghosts of U that the
+ * previous step's stage 4 wrote.  With Z4C_FLAG_GRAPH and a non-NULL stream,
+ * the four stages (ghost fills included) are captured once per (dt, stream)
+ * into two hipGraphs, the step for a call's first step and the step for the
+ * later ones, and replayed (captured again after a re-bind, a variant or a
+ * tracker change).  With
  * Z4C_FLAG_CHECK_FINITE, after the steps every value of U's active cells is
  * checked (one read of U, then the stream is synchronised); Z4C_ENONFINITE
  * if any is NaN or infinite (U is left as computed). */
