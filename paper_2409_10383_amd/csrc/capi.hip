@@ -178,6 +178,11 @@ int build_xlevel(z4c_pack* pk)
     const int nb = (int)pk->blk.size();
     pk->img_off.assign(nb, -1);
     std::vector<ProlongGroup> quads, pairs, singles;   // grouped prolongations
+    // ghosts of directions the stage path leaves alone (vmask): their items go
+    // after those of the other ghosts
+    std::vector<ProlongGroup> lquads, lpairs, lsingles;
+    std::vector<XferItem> xlate;
+    std::vector<ProlongItem> plate;
     // image rows (z-plane * m + y) some transfer reads, per source block
     // and the range of coarse x each such row needs
     std::vector<std::vector<uint8_t>> img_rows(nb);
@@ -218,13 +223,17 @@ int build_xlevel(z4c_pack* pk)
         for (int a = 0; a < 3; ++a) S0[a] = floor_div(B.ilo[a] - g, 2) - (np + 1);
         int64_t shoff = -1;
         std::vector<uint8_t> mark;
-        std::unordered_map<int64_t, size_t> pgmap;  // parent's child-(0,0,0) cell -> group
-        std::vector<ProlongGroup> bg;                // this block's groups
-        std::vector<int64_t> bkey;                   // and their keys
+        // per set (0: ghosts the stage path reads, 1: the others)
+        std::unordered_map<int64_t, size_t> pgmap[2];  // parent's child-(0,0,0) cell -> group
+        std::vector<ProlongGroup> bg[2];                // this block's groups
+        std::vector<int64_t> bkey[2];                   // and their keys
         for (int k = 0; k < E; ++k)
             for (int j = 0; j < E; ++j)
                 for (int i = 0; i < E; ++i) {
                     if (i >= g && i < g + n && j >= g && j < g + n && k >= g && k < g + n) continue;
+                    const int didx = ((k < g ? 0 : (k >= g + n ? 2 : 1)) * 3 + (j < g ? 0 : (j >= g + n ? 2 : 1))) * 3 +
+                                     (i < g ? 0 : (i >= g + n ? 2 : 1));
+                    const int late = (int)((pk->vmask[b] >> didx) & 1u);
                     const int64_t G[3] = {B.ilo[0] + i - g, B.ilo[1] + j - g, B.ilo[2] + k - g};
                     int64_t Gb[3] = {G[0], G[1], G[2]};
                     geo.bc(l, Gb);
@@ -243,7 +252,7 @@ int build_xlevel(z4c_pack* pk)
                         it.src_stride = pk->img_fstride[F];
                         it.kind = 1;
                         it.pad = 0;
-                        pk->xfer.push_back(it);
+                        (late ? xlate : pk->xfer).push_back(it);
                         continue;
                     }
                     const int64_t P[3] = {Gb[0] / 2, Gb[1] / 2, Gb[2] / 2};
@@ -314,8 +323,8 @@ int build_xlevel(z4c_pack* pk)
                         const int64_t d0 = D.off + ((int64_t)(k - cz) * E + (j - cy)) * E + (i - cx);
                         // key: child (0,0,0) index shifted by one (it can sit at -1)
                         const int64_t key = ((int64_t)(k - cz + 1) * (E + 2) + (j - cy + 1)) * (E + 2) + (i - cx + 1);
-                        auto itg = pgmap.find(key);
-                        if (itg == pgmap.end()) {
+                        auto itg = pgmap[late].find(key);
+                        if (itg == pgmap[late].end()) {
                             ProlongGroup pg;
                             pg.dst = d0;
                             pg.sh = shs;
@@ -323,11 +332,11 @@ int build_xlevel(z4c_pack* pk)
                             pg.se = (int32_t)SE;
                             pg.mask = 0;
                             pg.fstride = (int32_t)fstride;
-                            itg = pgmap.emplace(key, bg.size()).first;
-                            bg.push_back(pg);
-                            bkey.push_back(key);
+                            itg = pgmap[late].emplace(key, bg[late].size()).first;
+                            bg[late].push_back(pg);
+                            bkey[late].push_back(key);
                         }
-                        bg[itg->second].mask |= 1 << (cz * 4 + cy * 2 + cx);
+                        bg[late][itg->second].mask |= 1 << (cz * 4 + cy * 2 + cx);
                     } else {
                         ProlongItem pi;
                         pi.dst = dcell;
@@ -336,7 +345,7 @@ int build_xlevel(z4c_pack* pk)
                         pi.se = (int32_t)SE;
                         pi.parity = parity;
                         pi.pad = (int32_t)fstride;  // field stride of the shadow box
-                        pk->prol.push_back(pi);
+                        (late ? plate : pk->prol).push_back(pi);
                     }
                 }
         // neighbouring parents along y and z (child-(0,0,0) keys two rows or
@@ -346,39 +355,53 @@ int build_xlevel(z4c_pack* pk)
         // neighbouring parents along x, so a load still touches the lines of
         // one row
         const int64_t dy = 2 * (int64_t)(E + 2), dz = dy * (E + 2);
-        std::vector<uint8_t> used(bg.size(), 0);
-        auto partner = [&](size_t q, int64_t dk) -> int64_t {
-            const auto it2 = pgmap.find(bkey[q] + dk);
-            return (it2 == pgmap.end() || used[it2->second]) ? -1 : (int64_t)it2->second;
-        };
-        // (fours only for FP64: with 4-byte loads the wider thread costs more
-        // than the shared rows save)
-        for (size_t q = 0; q < bg.size() && pk->p.precision == Z4C_FP64; ++q) {
-            if (used[q]) continue;
-            const int64_t b1 = partner(q, dy), c1 = partner(q, dz), d1 = partner(q, dy + dz);
-            if (b1 < 0 || c1 < 0 || d1 < 0) continue;
-            ProlongGroup pg = bg[q];
-            pg.mask |= (bg[b1].mask << 8) | (bg[c1].mask << 16) | (bg[d1].mask << 24);
-            quads.push_back(pg);
-            used[q] = used[b1] = used[c1] = used[d1] = 1;
+        for (int set = 0; set < 2; ++set) {
+            const std::vector<ProlongGroup>& grp = bg[set];
+            const std::vector<int64_t>& keys = bkey[set];
+            const std::unordered_map<int64_t, size_t>& at = pgmap[set];
+            std::vector<ProlongGroup>& q4 = set ? lquads : quads;
+            std::vector<ProlongGroup>& q2 = set ? lpairs : pairs;
+            std::vector<ProlongGroup>& q1 = set ? lsingles : singles;
+            std::vector<uint8_t> used(grp.size(), 0);
+            auto partner = [&](size_t q, int64_t dk) -> int64_t {
+                const auto it2 = at.find(keys[q] + dk);
+                return (it2 == at.end() || used[it2->second]) ? -1 : (int64_t)it2->second;
+            };
+            // (fours only for FP64: with 4-byte loads the wider thread costs more
+            // than the shared rows save)
+            for (size_t q = 0; q < grp.size() && pk->p.precision == Z4C_FP64; ++q) {
+                if (used[q]) continue;
+                const int64_t b1 = partner(q, dy), c1 = partner(q, dz), d1 = partner(q, dy + dz);
+                if (b1 < 0 || c1 < 0 || d1 < 0) continue;
+                ProlongGroup pg = grp[q];
+                pg.mask |= (grp[b1].mask << 8) | (grp[c1].mask << 16) | (grp[d1].mask << 24);
+                q4.push_back(pg);
+                used[q] = used[b1] = used[c1] = used[d1] = 1;
+            }
+            for (size_t q = 0; q < grp.size(); ++q) {
+                if (used[q]) continue;
+                const int64_t o1 = partner(q, dy);
+                if (o1 < 0) continue;
+                ProlongGroup pg = grp[q];
+                pg.mask |= grp[o1].mask << 8;
+                q2.push_back(pg);
+                used[q] = used[o1] = 1;
+            }
+            for (size_t q = 0; q < grp.size(); ++q)
+                if (!used[q]) q1.push_back(grp[q]);
+            pk->nparent += (int64_t)grp.size();
         }
-        for (size_t q = 0; q < bg.size(); ++q) {
-            if (used[q]) continue;
-            const int64_t o1 = partner(q, dy);
-            if (o1 < 0) continue;
-            ProlongGroup pg = bg[q];
-            pg.mask |= bg[o1].mask << 8;
-            pairs.push_back(pg);
-            used[q] = used[o1] = 1;
-        }
-        for (size_t q = 0; q < bg.size(); ++q)
-            if (!used[q]) singles.push_back(bg[q]);
-        pk->nparent += (int64_t)bg.size();
     }
     // by kind, so that few waves mix them
     pk->pgrp = quads;
     pk->pgrp.insert(pk->pgrp.end(), pairs.begin(), pairs.end());
     pk->pgrp.insert(pk->pgrp.end(), singles.begin(), singles.end());
+    pk->npgrp_stage = (int64_t)pk->pgrp.size();
+    pk->pgrp.insert(pk->pgrp.end(), lquads.begin(), lquads.end());
+    pk->pgrp.insert(pk->pgrp.end(), lpairs.begin(), lpairs.end());
+    pk->pgrp.insert(pk->pgrp.end(), lsingles.begin(), lsingles.end());
+    pk->nprol_stage = (int64_t)pk->prol.size();
+    pk->prol.insert(pk->prol.end(), plate.begin(), plate.end());
     // image restriction work: per source block, runs of consecutive coarse
     // z-planes that need the same rows (first to last row some transfer
     // reads) and columns, split into row chunks that fit the LDS budget; a
@@ -432,6 +455,8 @@ int build_xlevel(z4c_pack* pk)
     // the same-level fill, and run beside them
     std::stable_partition(pk->xfer.begin(), pk->xfer.end(), [](const XferItem& it) { return it.kind == 2; });
     pk->nxfer_direct = std::count_if(pk->xfer.begin(), pk->xfer.end(), [](const XferItem& it) { return it.kind == 2; });
+    pk->nxfer_stage = (int64_t)pk->xfer.size();
+    pk->xfer.insert(pk->xfer.end(), xlate.begin(), xlate.end());
     return Z4C_OK;
 }
 
@@ -789,11 +814,13 @@ int z4c_pack_create(const z4c_params* params, const z4c_block* blocks, int32_t n
                 }
     }
 
+    // the cross-level lists put the items of ghosts the stage path leaves
+    // alone (vmask) last
+    build_virtual_halos(pk);
     if (pk->multilevel) {
         const int rc = build_xlevel(pk);
         if (rc) { delete pk; return rc; }
     }
-    build_virtual_halos(pk);
 
     // workspace
     size_t o = 0;
@@ -1025,10 +1052,10 @@ static int fill_impl(z4c_pack* pk, int32_t reg, void* stream, bool virt, bool pu
         x.prol = reinterpret_cast<const ProlongItem*>(pk->ws + pk->ws_prol);
         x.rw = reinterpret_cast<const double*>(pk->ws + pk->ws_w);
         x.pw = x.rw + 64;
-        x.nxfer = (int64_t)pk->xfer.size();
-        x.nprol = (int64_t)pk->prol.size();
+        x.nxfer = virt ? pk->nxfer_stage : (int64_t)pk->xfer.size();
+        x.nprol = virt ? pk->nprol_stage : (int64_t)pk->prol.size();
         x.pgrp = reinterpret_cast<const ProlongGroup*>(pk->ws + pk->ws_pgrp);
-        x.npgrp = (int64_t)pk->pgrp.size();
+        x.npgrp = virt ? pk->npgrp_stage : (int64_t)pk->pgrp.size();
         x.npts = pk->p.nghost + 1;
     }
     const XferItem* xf = x.xfer;

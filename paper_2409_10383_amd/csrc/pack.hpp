@@ -23,6 +23,9 @@ struct z4c_pack {
     // cross-level fill tables
     std::vector<XferItem> xfer;       // copies from active cells first, then from images
     int64_t nxfer_direct = 0;         // of which from active cells
+    // the stage path's fill stops at these counts: the items after them write
+    // ghosts of directions the stage kernel reads in place or never reads
+    int64_t nxfer_stage = 0, nprol_stage = 0, npgrp_stage = 0;
     std::vector<ProlongItem> prol;
     std::vector<ProlongGroup> pgrp;   // parents by four (y and z, FP64), by two (y), then single
     int64_t nparent = 0;              // coarse parents of grouped prolongations
